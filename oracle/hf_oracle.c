@@ -1,0 +1,578 @@
+/*
+ * Hilbert-forest ORACLE -- test infrastructure only.
+ *
+ * A plain, slow, obviously correct CPU implementation of what the Hilbert
+ * forest computes (Imamura et al., "Hilbert Forest in the SISAP 2025 Indexing
+ * Challenge", arXiv 2508.21682).  Only the tests, the package smoke check and
+ * the benchmark's CPU-baseline leg may load it.  It shares no code with the
+ * HIP library: keys are computed in full (all d*B bits) by Skilling's
+ * transform, sorts use qsort on full keys, node tests are found by toggling
+ * bits, sets are formed with marker arrays, scores are FP64.
+ *
+ * Parity status of each function is given in its header comment.  All
+ * readings of places where the paper is silent are the ones the library
+ * documents (power-of-two 8-bit quantiser, SplitMix64 curve seeds, axis
+ * permutation + reflection, leaf midpoint window, set semantics for C1).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define HFO_SKETCH_WORDS 8 /* 512-bit sketches */
+
+/* ------------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number     */
+/* generators", OOPSLA 2014): add the golden-gamma constant, then mix.       */
+/* Pinned by the published first outputs for seed 0 (tests).                 */
+/* ------------------------------------------------------------------------ */
+static uint64_t sm64_next(uint64_t *state) {
+  uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t hfo_splitmix64(uint64_t seed, int64_t index) {
+  uint64_t s = seed, z = 0;
+  for (int64_t i = 0; i <= index; ++i) z = sm64_next(&s);
+  return z;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Curves, one per tree (Alg. 1 "randomized axis orders"; Alg. 2 "randomly   */
+/* permute coordinate axes").  One SplitMix64 stream seeded with `seed` is   */
+/* consumed tree after tree: first a Fisher-Yates shuffle of the identity    */
+/* (for i = d-1 down to 1: j = next mod (i+1), swap), then ceil(d/64) words  */
+/* whose bits (LSB first) say which tree axes are reflected (x -> 255 - x).  */
+/* Pinned: permutation property + published SplitMix64 outputs.             */
+/* ------------------------------------------------------------------------ */
+void hfo_curves(uint64_t seed, int32_t T, int32_t d, int32_t *perm, uint8_t *refl) {
+  uint64_t s = seed;
+  for (int32_t t = 0; t < T; ++t) {
+    int32_t *p = perm + (int64_t)t * d;
+    for (int32_t i = 0; i < d; ++i) p[i] = i;
+    for (int32_t i = d - 1; i >= 1; --i) {
+      uint64_t j = sm64_next(&s) % (uint64_t)(i + 1);
+      int32_t tmp = p[i];
+      p[i] = p[j];
+      p[j] = tmp;
+    }
+    for (int32_t w = 0; w < (d + 63) / 64; ++w) {
+      uint64_t bits = sm64_next(&s);
+      for (int32_t b = 0; b < 64 && w * 64 + b < d; ++b)
+        refl[(int64_t)t * d + w * 64 + b] = (uint8_t)((bits >> b) & 1u);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stored values.  dtype 0 = IEEE binary16, 1 = binary32; both are exact in  */
+/* binary64.  Pinned against numpy's float16 conversion for all 65536 codes. */
+/* ------------------------------------------------------------------------ */
+double hfo_f16_to_f64(uint16_t h) {
+  int s = h >> 15, e = (h >> 10) & 31, m = h & 1023;
+  double v;
+  if (e == 0)
+    v = ldexp((double)m, -24);
+  else if (e == 31)
+    v = m ? NAN : INFINITY;
+  else
+    v = ldexp((double)(m + 1024), e - 25);
+  return s ? -v : v;
+}
+
+static double val(const void *x, int32_t dtype, int64_t i) {
+  if (dtype == 0) return hfo_f16_to_f64(((const uint16_t *)x)[i]);
+  return (double)((const float *)x)[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* 8-bit ordering codes (Alg. 1 / Alg. 2 "vector quantization"; the paper    */
+/* gives no codec for the ordering, so one power-of-two scale is used):      */
+/*   e = largest integer in [-8, 24] with 2^e*max < 128 and 2^e*min >= -128  */
+/*       over the data (-8 if none);  u = clamp(floor(x*2^e) + 128, 0, 255). */
+/* Returns INT32_MIN if any value is not finite.                             */
+/* Pinned: exact by construction (power-of-two scale, floor); tests check    */
+/* the defining inequalities and hand-computed codes.                        */
+/* ------------------------------------------------------------------------ */
+int32_t hfo_quant_exp(const void *x, int32_t dtype, int64_t n) {
+  double mx = -INFINITY, mn = INFINITY;
+  for (int64_t i = 0; i < n; ++i) {
+    double v = val(x, dtype, i);
+    if (!isfinite(v)) return INT32_MIN;
+    if (v > mx) mx = v;
+    if (v < mn) mn = v;
+  }
+  if (n == 0) return 24;
+  for (int32_t e = 24; e >= -8; --e)
+    if (ldexp(mx, e) < 128.0 && ldexp(mn, e) >= -128.0) return e;
+  return -8;
+}
+
+void hfo_quantize(const void *x, int32_t dtype, int64_t n, int32_t e, uint8_t *out) {
+  for (int64_t i = 0; i < n; ++i) {
+    double f = floor(ldexp(val(x, dtype, i), e)) + 128.0;
+    out[i] = (uint8_t)(f < 0.0 ? 0.0 : (f > 255.0 ? 255.0 : f));
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hilbert index by Skilling's transform (J. Skilling, "Programming the      */
+/* Hilbert curve", AIP Conf. Proc. 707, 2004), restated:                     */
+/*  1. for levels L = B-1 down to 1 (mask P = 2^L - 1), for axes i = 0..d-1: */
+/*     if bit L of X[i] is set, invert the low bits of X[0] (X[0] ^= P),     */
+/*     otherwise exchange the low bits of X[0] and X[i];                     */
+/*  2. Gray-encode: X[i] ^= X[i-1] for i = 1..d-1, then XOR every axis with  */
+/*     t = XOR of (2^L - 1) over the levels L >= 1 where X[d-1] has bit L;   */
+/*  3. read the bits level-major, MSB first: key bit (B-1-L)*d + j is bit L  */
+/*     of X[j].  Words hold 64 key bits each, key bit 0 in the word's MSB.   */
+/* The Hilbert sort (Section 2) orders points by this index.                 */
+/* Pinned: bijection, unit steps, sub-cube contiguity and origin start for   */
+/* small (d, B); B = 1 is the Gray code; d = 1 is the identity; the 2-D      */
+/* order-2 curve against a hand-drawn table.                                 */
+/* ------------------------------------------------------------------------ */
+void hfo_key(const uint8_t *v, int32_t d, int32_t B, uint64_t *key) {
+  uint8_t *X = (uint8_t *)malloc((size_t)d);
+  memcpy(X, v, (size_t)d);
+  for (int32_t L = B - 1; L >= 1; --L) {
+    uint8_t Q = (uint8_t)(1u << L), P = (uint8_t)(Q - 1u);
+    for (int32_t i = 0; i < d; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        uint8_t t = (uint8_t)((X[0] ^ X[i]) & P);
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  for (int32_t i = 1; i < d; ++i) X[i] ^= X[i - 1];
+  uint8_t t = 0;
+  for (int32_t L = B - 1; L >= 1; --L)
+    if (X[d - 1] & (1u << L)) t ^= (uint8_t)((1u << L) - 1u);
+  for (int32_t i = 0; i < d; ++i) X[i] ^= t;
+  int64_t words = ((int64_t)d * B + 63) / 64;
+  memset(key, 0, (size_t)words * 8);
+  for (int32_t L = B - 1; L >= 0; --L)
+    for (int32_t j = 0; j < d; ++j) {
+      int64_t b = (int64_t)(B - 1 - L) * d + j;
+      if ((X[j] >> L) & 1u) key[b >> 6] |= 1ull << (63 - (b & 63));
+    }
+  free(X);
+}
+
+/* Tree coordinates: v[i] = u[perm[i]] XOR (255 * refl[i]). */
+static void tree_coords(const uint8_t *u, int32_t d, const int32_t *perm, const uint8_t *refl,
+                        uint8_t *v) {
+  for (int32_t i = 0; i < d; ++i) v[i] = (uint8_t)(u[perm[i]] ^ (refl[i] ? 0xFFu : 0u));
+}
+
+void hfo_tree_keys(const uint8_t *codes, int64_t N, int32_t d, const int32_t *perm,
+                   const uint8_t *refl, uint64_t *keys) {
+  int64_t W = ((int64_t)d * 8 + 63) / 64;
+#pragma omp parallel
+  {
+    uint8_t *v = (uint8_t *)malloc((size_t)d);
+#pragma omp for schedule(static)
+    for (int64_t p = 0; p < N; ++p) {
+      tree_coords(codes + p * d, d, perm, refl, v);
+      hfo_key(v, d, 8, keys + p * W);
+    }
+    free(v);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hilbert sort (Section 2): order = argsort by (key, id), keys compared as  */
+/* bit strings.  Pinned: output is a permutation with non-decreasing keys    */
+/* and ids increasing among equal keys (checked independently in tests).     */
+/* ------------------------------------------------------------------------ */
+static const uint64_t *g_sort_keys;
+static int64_t g_sort_words;
+
+static int cmp_key_id(const void *a, const void *b) {
+  uint32_t ia = *(const uint32_t *)a, ib = *(const uint32_t *)b;
+  const uint64_t *ka = g_sort_keys + (int64_t)ia * g_sort_words;
+  const uint64_t *kb = g_sort_keys + (int64_t)ib * g_sort_words;
+  for (int64_t w = 0; w < g_sort_words; ++w)
+    if (ka[w] != kb[w]) return ka[w] < kb[w] ? -1 : 1;
+  return ia < ib ? -1 : (ia > ib ? 1 : 0);
+}
+
+void hfo_sort(const uint64_t *keys, int64_t N, int32_t W, uint32_t *order) {
+  for (int64_t i = 0; i < N; ++i) order[i] = (uint32_t)i;
+  g_sort_keys = keys;
+  g_sort_words = W;
+  qsort(order, (size_t)N, sizeof(uint32_t), cmp_key_id);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Leaf-compressed Hilbert tree (Section 2 "Hilbert tree"; Section 3.1 leaf  */
+/* compression of subtrees of about M points).  Read as a binary trie over   */
+/* the sorted keys:                                                          */
+/*   [lo,hi) is a leaf if hi-lo <= M or all its keys are equal; otherwise    */
+/*   b = first bit where the keys of order[lo] and order[hi-1] differ,       */
+/*   m = first index in [lo,hi) whose key has bit b set, children [lo,m),    */
+/*   [m,hi).  The node test (a, L, flip) says: key bit b of any point in the */
+/*   range equals bit L of its code on data axis a, XOR flip.  It is found   */
+/*   by brute force: the unique tree axis j such that toggling bit L of      */
+/*   v[order[lo]][j] keeps key bits < b and flips bit b; a = perm[j].        */
+/* Layout: pre-order, left subtree first; two u32 words per node:            */
+/*   internal: w0 = index of the right child, w1 = a | L<<16 | flip<<19;     */
+/*   leaf:     w0 = lo,                       w1 = 1<<31 | (hi-lo).          */
+/* Returns the node count, or -1 if `cap` is too small, -2 if a node test is */
+/* not unique (cannot happen for Skilling keys; kept as an assertion).       */
+/* Pinned by invariants in tests (ranges partition [0,N), split bits, every  */
+/* data point descends to the leaf holding it, test valid at both ends).     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  const uint64_t *keys;
+  const uint32_t *order;
+  int64_t W;
+  int32_t d, M;
+  uint32_t *nodes;
+  int64_t cap, count;
+  int64_t *pending; /* node index -> (lo, b) for internal nodes, to fill tests later */
+  int64_t *pend_lo, *pend_b;
+  int64_t npend;
+} trie_ctx;
+
+static int keybit(const uint64_t *k, int64_t b) { return (int)((k[b >> 6] >> (63 - (b & 63))) & 1u); }
+
+static int64_t first_diff(const uint64_t *a, const uint64_t *b, int64_t W) {
+  for (int64_t w = 0; w < W; ++w)
+    if (a[w] != b[w]) {
+      uint64_t x = a[w] ^ b[w];
+      int64_t z = 0;
+      while (!((x >> (63 - z)) & 1u)) ++z;
+      return w * 64 + z;
+    }
+  return -1;
+}
+
+static int64_t trie_rec(trie_ctx *c, int64_t lo, int64_t hi) {
+  int64_t me = c->count++;
+  if (me >= c->cap) return -1;
+  const uint64_t *klo = c->keys + (int64_t)c->order[lo] * c->W;
+  const uint64_t *khi = c->keys + (int64_t)c->order[hi - 1] * c->W;
+  int64_t b = (hi - lo <= c->M) ? -1 : first_diff(klo, khi, c->W);
+  if (b < 0) {
+    c->nodes[2 * me] = (uint32_t)lo;
+    c->nodes[2 * me + 1] = 0x80000000u | (uint32_t)(hi - lo);
+    return 0;
+  }
+  int64_t m = lo;
+  while (!keybit(c->keys + (int64_t)c->order[m] * c->W, b)) ++m;
+  c->pending[c->npend] = me;
+  c->pend_lo[c->npend] = lo;
+  c->pend_b[c->npend] = b;
+  c->npend++;
+  if (trie_rec(c, lo, m) < 0) return -1;
+  c->nodes[2 * me] = (uint32_t)c->count; /* right child comes next in pre-order */
+  return trie_rec(c, m, hi);
+}
+
+int64_t hfo_trie(const uint64_t *keys, const uint32_t *order, int64_t N, int32_t d, int32_t M,
+                 const uint8_t *codes, const int32_t *perm, const uint8_t *refl, uint32_t *nodes,
+                 int64_t cap) {
+  trie_ctx c;
+  c.keys = keys;
+  c.order = order;
+  c.W = ((int64_t)d * 8 + 63) / 64;
+  c.d = d;
+  c.M = M;
+  c.nodes = nodes;
+  c.cap = cap;
+  c.count = 0;
+  c.npend = 0;
+  c.pending = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap + 1));
+  c.pend_lo = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap + 1));
+  c.pend_b = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap + 1));
+  int64_t rc = trie_rec(&c, 0, N);
+  int bad = 0;
+  if (rc >= 0) {
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+    for (int64_t q = 0; q < c.npend; ++q) {
+      int64_t me = c.pending[q], b = c.pend_b[q];
+      uint32_t p = order[c.pend_lo[q]];
+      int32_t L = 7 - (int32_t)(b / d);
+      uint8_t *v = (uint8_t *)malloc((size_t)d);
+      uint64_t *k0 = (uint64_t *)malloc((size_t)c.W * 8);
+      uint64_t *k1 = (uint64_t *)malloc((size_t)c.W * 8);
+      tree_coords(codes + (int64_t)p * d, d, perm, refl, v);
+      hfo_key(v, d, 8, k0);
+      int found = -1, nfound = 0;
+      for (int32_t j = 0; j < d; ++j) {
+        v[j] ^= (uint8_t)(1u << L);
+        hfo_key(v, d, 8, k1);
+        v[j] ^= (uint8_t)(1u << L);
+        int64_t f = first_diff(k0, k1, c.W);
+        if (f == b) {
+          found = j;
+          ++nfound;
+        }
+      }
+      if (nfound != 1) {
+        bad = 1;
+      } else {
+        int32_t a = perm[found];
+        int flip = keybit(k0, b) ^ ((codes[(int64_t)p * d + a] >> L) & 1);
+        nodes[2 * me + 1] = (uint32_t)a | ((uint32_t)L << 16) | ((uint32_t)flip << 19);
+      }
+      free(v);
+      free(k0);
+      free(k1);
+    }
+  }
+  free(c.pending);
+  free(c.pend_lo);
+  free(c.pend_b);
+  if (rc < 0) return -1;
+  if (bad) return -2;
+  return c.count;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collective descent (Section 3.1 "simulate the Hilbert sort for all        */
+/* queries"; Alg. 1 first stage).  From the root, bit = ((u_q[a] >> L) & 1)  */
+/* ^ flip; 0 goes left (next node), 1 goes right.  At the leaf [lo,hi) the   */
+/* query's position is read as the leaf midpoint and the k1 candidates as    */
+/* the centred window: s = clamp(floor((lo+hi)/2) - floor(k1/2), 0,          */
+/* max(0, N-k1)).  Pinned: every data point descends to its own leaf (test). */
+/* ------------------------------------------------------------------------ */
+void hfo_window_starts(const uint32_t *nodes, const uint8_t *qcodes, int64_t nq, int32_t d,
+                       int64_t N, int32_t k1, uint32_t *out, int64_t out_stride) {
+  for (int64_t q = 0; q < nq; ++q) {
+    const uint8_t *u = qcodes + q * d;
+    int64_t idx = 0;
+    for (;;) {
+      uint32_t w0 = nodes[2 * idx], w1 = nodes[2 * idx + 1];
+      if (w1 >> 31) {
+        int64_t mid = (int64_t)w0 + (int64_t)((w1 & 0x7FFFFFFFu) >> 1);
+        int64_t s = mid - k1 / 2, smax = N - k1 > 0 ? N - k1 : 0;
+        if (s < 0) s = 0;
+        if (s > smax) s = smax;
+        out[q * out_stride] = (uint32_t)s;
+        break;
+      }
+      uint32_t a = w1 & 0xFFFFu, L = (w1 >> 16) & 7u, flip = (w1 >> 19) & 1u;
+      uint32_t bit = ((u[a] >> L) & 1u) ^ flip;
+      idx = bit ? (int64_t)w0 : idx + 1;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 512-bit sign-of-random-projection sketches (Section 3.1 uses binary       */
+/* sketches compared by Hamming distance; their construction is not given). */
+/* R[j][i] in {-1,+1} is bit (j*d + i) of the concatenated SplitMix64        */
+/* outputs seeded with `sketch_seed` (LSB first, 1 -> +1);                   */
+/* xq_i = clamp(rne(x_i * 2^(e+5)), -8191, 8191) with e the data's code      */
+/* exponent; z_j = sum_i R[j][i]*xq_i (exact integer); sketch bit j =        */
+/* [z_j >= 0], stored in word j/64 at bit j%64.                              */
+/* Pinned: sign symmetry sketch(-x) = ~sketch(x) where no z_j is 0, the     */
+/* integer sum against an independent numpy matmul (tests).                  */
+/* ------------------------------------------------------------------------ */
+void hfo_srp(const void *x, int32_t dtype, int64_t N, int32_t d, int32_t e, uint64_t sketch_seed,
+             uint64_t *out) {
+  int64_t nbits = 512LL * d, nw = (nbits + 63) / 64;
+  uint64_t *R = (uint64_t *)malloc((size_t)nw * 8);
+  uint64_t s = sketch_seed;
+  for (int64_t w = 0; w < nw; ++w) R[w] = sm64_next(&s);
+#pragma omp parallel
+  {
+    int64_t *xq = (int64_t *)malloc(sizeof(int64_t) * (size_t)d);
+#pragma omp for schedule(static)
+    for (int64_t p = 0; p < N; ++p) {
+      for (int32_t i = 0; i < d; ++i) {
+        double r = nearbyint(ldexp(val(x, dtype, p * d + i), e + 5));
+        if (r > 8191.0) r = 8191.0;
+        if (r < -8191.0) r = -8191.0;
+        xq[i] = (int64_t)r;
+      }
+      uint64_t *o = out + p * HFO_SKETCH_WORDS;
+      memset(o, 0, HFO_SKETCH_WORDS * 8);
+      for (int32_t j = 0; j < 512; ++j) {
+        int64_t z = 0;
+        for (int32_t i = 0; i < d; ++i) {
+          int64_t b = (int64_t)j * d + i;
+          z += ((R[b >> 6] >> (b & 63)) & 1u) ? xq[i] : -xq[i];
+        }
+        if (z >= 0) o[j >> 6] |= 1ull << (j & 63);
+      }
+    }
+    free(xq);
+  }
+  free(R);
+}
+
+static int hamming(const uint64_t *a, const uint64_t *b) {
+  int h = 0;
+  for (int w = 0; w < HFO_SKETCH_WORDS; ++w) h += __builtin_popcountll(a[w] ^ b[w]);
+  return h;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Second stage and final selection of Alg. 1, one query at a time:          */
+/*   C1 = union over trees of tree_perm[t][s .. s+k1) (a set of master       */
+/*        positions; the paper's count n*k1 includes duplicates);            */
+/*   C2 = first min(k2, |C1|) of C1 ordered by (Hamming(sk_q, sk_r), r);     */
+/*   E  = union over r in C2 of [max(0, r-h), min(N-1, r+h)] (master order); */
+/*   S  = top-k of E by (inner product desc, r asc) in FP64, mapped to ids.  */
+/* x_pos(r) = X[pos2id[r]].  Pinned: T=1, k1>=N, k2>=N, h=0 reduces to the   */
+/* exact brute-force k-NN (tests); C1/C2/E by set algebra on tiny inputs.    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t key;
+  int64_t r;
+  double s;
+} cand;
+
+static int cmp_ham_pos(const void *a, const void *b) {
+  const cand *x = (const cand *)a, *y = (const cand *)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->r < y->r ? -1 : (x->r > y->r ? 1 : 0);
+}
+
+static int cmp_score_desc_pos(const void *a, const void *b) {
+  const cand *x = (const cand *)a, *y = (const cand *)b;
+  if (x->s != y->s) return x->s > y->s ? -1 : 1;
+  return x->r < y->r ? -1 : (x->r > y->r ? 1 : 0);
+}
+
+void hfo_search_stage2(const void *X, int32_t dtype, int64_t N, int32_t d, const uint32_t *pos2id,
+                       const uint32_t *tree_perm, int32_t T, const uint32_t *winstart,
+                       const uint64_t *sk_pos, const void *Q, const uint64_t *qsk, int64_t nq,
+                       int32_t k1, int32_t k2, int32_t h, int32_t k, int32_t *ids, double *scores,
+                       uint32_t *c2, int32_t *c2n, int32_t *c1n, int32_t *en) {
+  int64_t len = k1 < N ? k1 : N;
+#pragma omp parallel
+  {
+    uint8_t *mark = (uint8_t *)calloc((size_t)N, 1);
+    cand *buf = (cand *)malloc(sizeof(cand) * (size_t)(T * len + (int64_t)k2 * (2 * h + 1) + 1));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nq; ++q) {
+      const uint64_t *sq = qsk + q * HFO_SKETCH_WORDS;
+      int64_t n1 = 0;
+      for (int32_t t = 0; t < T; ++t) {
+        const uint32_t *P = tree_perm + (int64_t)t * N;
+        int64_t s = winstart[q * T + t];
+        for (int64_t i = s; i < s + len; ++i) {
+          uint32_t r = P[i];
+          if (!mark[r]) {
+            mark[r] = 1;
+            buf[n1].r = r;
+            buf[n1].key = hamming(sq, sk_pos + (int64_t)r * HFO_SKETCH_WORDS);
+            ++n1;
+          }
+        }
+      }
+      for (int64_t i = 0; i < n1; ++i) mark[buf[i].r] = 0;
+      qsort(buf, (size_t)n1, sizeof(cand), cmp_ham_pos);
+      int64_t n2 = n1 < k2 ? n1 : k2;
+      if (c2)
+        for (int64_t i = 0; i < k2; ++i) c2[q * k2 + i] = i < n2 ? (uint32_t)buf[i].r : 0xFFFFFFFFu;
+      if (c2n) c2n[q] = (int32_t)n2;
+      if (c1n) c1n[q] = (int32_t)n1;
+      /* expansion in master order */
+      cand *E = buf + n2;
+      int64_t ne = 0;
+      for (int64_t i = 0; i < n2; ++i) {
+        int64_t r = buf[i].r, a = r - h < 0 ? 0 : r - h, z = r + h > N - 1 ? N - 1 : r + h;
+        for (int64_t x = a; x <= z; ++x)
+          if (!mark[x]) {
+            mark[x] = 1;
+            E[ne].r = x;
+            ++ne;
+          }
+      }
+      for (int64_t i = 0; i < ne; ++i) mark[E[i].r] = 0;
+      if (en) en[q] = (int32_t)ne;
+      for (int64_t i = 0; i < ne; ++i) {
+        int64_t row = (int64_t)pos2id[E[i].r];
+        double acc = 0.0;
+        for (int32_t j = 0; j < d; ++j) acc += val(Q, dtype, q * d + j) * val(X, dtype, row * d + j);
+        E[i].s = acc;
+      }
+      qsort(E, (size_t)ne, sizeof(cand), cmp_score_desc_pos);
+      for (int32_t i = 0; i < k; ++i) {
+        ids[q * k + i] = i < ne ? (int32_t)pos2id[E[i].r] : -1;
+        scores[q * k + i] = i < ne ? E[i].s : -INFINITY;
+      }
+    }
+    free(mark);
+    free(buf);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* k-NN graph rows (Alg. 2), for selected rows p only:                       */
+/*   C1(p) = union over orders t of order_t[i-w .. i+w] without p, i being   */
+/*           p's rank in order t (window clipped to the array);              */
+/*   k2 > 0: C2(p) = first k2 of C1(p) by (Hamming, id); else C2 = C1;       */
+/*   S(p)  = top-k of C2(p) by (cosine desc, id asc) in FP64.                */
+/* Pinned: w >= N reduces to the exact brute-force graph (tests).            */
+/* ------------------------------------------------------------------------ */
+static int cmp_key_r(const void *a, const void *b) { return cmp_ham_pos(a, b); }
+
+void hfo_graph_rows(const void *X, int32_t dtype, int64_t N, int32_t d, const uint32_t *orders,
+                    int32_t n, int32_t w, const int64_t *rows, int64_t nrows, int32_t k, int32_t k2,
+                    const uint64_t *sk, int32_t *out_ids, double *out_scores, int32_t *c1n) {
+  uint32_t *rank = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N * n));
+  for (int32_t t = 0; t < n; ++t)
+    for (int64_t i = 0; i < N; ++i) rank[(int64_t)t * N + orders[(int64_t)t * N + i]] = (uint32_t)i;
+  double *norm = (double *)malloc(sizeof(double) * (size_t)N);
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < N; ++p) {
+    double a = 0.0;
+    for (int32_t j = 0; j < d; ++j) {
+      double v = val(X, dtype, p * d + j);
+      a += v * v;
+    }
+    norm[p] = sqrt(a);
+  }
+#pragma omp parallel
+  {
+    uint8_t *mark = (uint8_t *)calloc((size_t)N, 1);
+    cand *buf = (cand *)malloc(sizeof(cand) * (size_t)((int64_t)n * (2 * w + 1) + 1));
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t ri = 0; ri < nrows; ++ri) {
+      int64_t p = rows[ri], n1 = 0;
+      for (int32_t t = 0; t < n; ++t) {
+        int64_t i = rank[(int64_t)t * N + p];
+        int64_t a = i - w < 0 ? 0 : i - w, z = i + w > N - 1 ? N - 1 : i + w;
+        for (int64_t j = a; j <= z; ++j) {
+          uint32_t c = orders[(int64_t)t * N + j];
+          if ((int64_t)c == p || mark[c]) continue;
+          mark[c] = 1;
+          buf[n1].r = c;
+          buf[n1].key = sk ? hamming(sk + p * HFO_SKETCH_WORDS, sk + (int64_t)c * HFO_SKETCH_WORDS) : 0;
+          ++n1;
+        }
+      }
+      for (int64_t i = 0; i < n1; ++i) mark[buf[i].r] = 0;
+      if (c1n) c1n[ri] = (int32_t)n1;
+      int64_t n2 = n1;
+      if (k2 > 0) {
+        qsort(buf, (size_t)n1, sizeof(cand), cmp_key_r);
+        if (n2 > k2) n2 = k2;
+      }
+      for (int64_t i = 0; i < n2; ++i) {
+        int64_t c = buf[i].r;
+        double acc = 0.0;
+        for (int32_t j = 0; j < d; ++j) acc += val(X, dtype, p * d + j) * val(X, dtype, c * d + j);
+        buf[i].s = acc / (norm[p] * norm[c]);
+      }
+      qsort(buf, (size_t)n2, sizeof(cand), cmp_score_desc_pos);
+      for (int32_t i = 0; i < k; ++i) {
+        out_ids[ri * k + i] = i < n2 ? (int32_t)buf[i].r : -1;
+        out_scores[ri * k + i] = i < n2 ? buf[i].s : -INFINITY;
+      }
+    }
+    free(mark);
+    free(buf);
+  }
+  free(rank);
+  free(norm);
+}

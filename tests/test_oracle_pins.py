@@ -1,0 +1,412 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types an oracle formula: each checks a property, a closed
+form, a special case that reduces to a textbook object, a hand-drawn table or
+brute force on tiny inputs.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import datagen
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line)
+    return rows
+
+
+# ----------------------------------------------------------------- SplitMix64
+def test_splitmix64_published_outputs(orc):
+    want = [int(v, 16) for v in _read_golden("splitmix64_seed0.txt")]
+    assert [orc.splitmix64(0, i) for i in range(3)] == want
+
+
+def test_curves_are_permutations_and_seeded(orc):
+    perm, refl = orc.curves(7, 5, 384)
+    for t in range(5):
+        assert sorted(perm[t].tolist()) == list(range(384))
+    assert set(np.unique(refl).tolist()) <= {0, 1}
+    assert 100 < refl.sum() / 5 < 284  # about half the axes reflected
+    p2, r2 = orc.curves(7, 5, 384)
+    assert (p2 == perm).all() and (r2 == refl).all()
+    p3, _ = orc.curves(8, 5, 384)
+    assert (p3 != perm).any()
+    # tree t of a longer forest equals tree t of a shorter one (one stream, tree order)
+    p4, r4 = orc.curves(7, 3, 384)
+    assert (p4 == perm[:3]).all() and (r4 == refl[:3]).all()
+
+
+def test_curves_fisher_yates_first_draw(orc):
+    """d=2: the single Fisher-Yates draw j = next mod 2 decides the swap."""
+    perm, refl = orc.curves(0, 1, 2)
+    j = orc.splitmix64(0, 0) % 2
+    assert perm[0].tolist() == ([1, 0] if j == 0 else [0, 1])
+    bits = orc.splitmix64(0, 1)
+    assert refl[0].tolist() == [bits & 1, (bits >> 1) & 1]
+
+
+# ----------------------------------------------------------------- stored values
+def test_f16_to_f64_all_codes(orc):
+    lib = orc.lib()
+    codes = np.arange(65536, dtype=np.uint16)
+    ref = codes.view(np.float16).astype(np.float64)
+    got = np.array([lib.hfo_f16_to_f64(int(c)) for c in codes])
+    fin = np.isfinite(ref)
+    assert (got[fin] == ref[fin]).all()
+    assert (np.isnan(got) == np.isnan(ref)).all()
+    assert (got[np.isinf(ref)] == ref[np.isinf(ref)]).all()
+
+
+# ----------------------------------------------------------------- quantiser
+def test_quant_exp_defining_inequalities(orc):
+    rng = np.random.default_rng(1)
+    for scale in [1e-3, 0.05, 0.3, 1.0, 7.0, 100.0, 3e4]:
+        x = (rng.standard_normal((50, 17)) * scale).astype(np.float32)
+        e = orc.quant_exp(x)
+        assert -8 <= e <= 24
+        ok = lambda ee: (2.0 ** ee) * x.max() < 128 and (2.0 ** ee) * x.min() >= -128
+        if ok(-8):
+            assert ok(e)
+            assert e == 24 or not ok(e + 1)
+        else:  # no exponent fits: the coarsest one, codes clamp
+            assert e == -8
+
+
+def test_quant_exp_nonfinite(orc):
+    x = np.ones((4, 4), np.float32)
+    x[2, 1] = np.inf
+    assert orc.quant_exp(x) == np.iinfo(np.int32).min
+
+
+def test_quantize_hand_values(orc):
+    x = np.array([0.0, -0.0, 0.5, -0.5, 0.49609375, -0.001, 1e9, -1e9], np.float32)
+    # e = 8: 0 -> 128, -0 -> 128, 0.5*256=128 -> 256 -> clamp 255, -128 -> 0,
+    # 0.49609375*256 = 127 -> 255, -0.256 -> floor -1 -> 127, huge -> 255, tiny -> 0
+    got = orc.quantize(x, 8)
+    assert got.tolist() == [128, 128, 255, 0, 255, 127, 255, 0]
+    # floor, not round: 0.9/256 below one step stays in the same cell
+    assert orc.quantize(np.array([0.9 / 256], np.float32), 8).tolist() == [128]
+
+
+# ----------------------------------------------------------------- Skilling keys
+@pytest.mark.parametrize("d,B", [(1, 1), (1, 4), (2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2),
+                                 (3, 3), (4, 2), (4, 3), (5, 2)])
+def test_hilbert_bijection_adjacency_subcubes(orc, d, B):
+    side = 1 << B
+    cells = list(itertools.product(range(side), repeat=d))
+    idx = {c: orc.hilbert_index_int(c, B) for c in cells}
+    # bijection onto [0, 2^(dB))
+    assert sorted(idx.values()) == list(range(side ** d))
+    inv = {v: c for c, v in idx.items()}
+    # starts at the origin
+    assert inv[0] == (0,) * d
+    # unit steps: consecutive indices are grid neighbours
+    for h in range(side ** d - 1):
+        a, b = inv[h], inv[h + 1]
+        assert sum(abs(x - y) for x, y in zip(a, b)) == 1, (h, a, b)
+    # every aligned sub-cube of side 2^l is one contiguous index interval
+    for lev in range(1, B):
+        s = 1 << lev
+        groups = {}
+        for c, v in idx.items():
+            groups.setdefault(tuple(x // s for x in c), []).append(v)
+        for vs in groups.values():
+            vs.sort()
+            assert vs[-1] - vs[0] == len(vs) - 1
+
+
+def test_hilbert_2d_order2_hand_table(orc):
+    cells = [tuple(int(t) for t in r.split()) for r in _read_golden("hilbert_2d_order2.txt")]
+    order = sorted(itertools.product(range(4), repeat=2), key=lambda c: orc.hilbert_index_int(c, 2))
+    assert order == cells
+
+
+def test_hilbert_order1_2d_u_shape(orc):
+    order = sorted(itertools.product(range(2), repeat=2), key=lambda c: orc.hilbert_index_int(c, 1))
+    assert order == [(0, 0), (0, 1), (1, 1), (1, 0)]
+
+
+@pytest.mark.parametrize("d", [1, 2, 5, 10])
+def test_hilbert_B1_is_gray_code(orc, d):
+    """B=1: the curve visits the cube corners in binary-reflected Gray-code order, axis 0 MSB."""
+    for h in range(1 << d):
+        g = h ^ (h >> 1)
+        corner = [(g >> (d - 1 - j)) & 1 for j in range(d)]
+        assert orc.hilbert_index_int(corner, 1) == h
+
+
+def test_hilbert_B1_gray_code_d384(orc):
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        h = int.from_bytes(rng.bytes(48), "big")
+        g = h ^ (h >> 1)
+        corner = [(g >> (383 - j)) & 1 for j in range(384)]
+        assert orc.hilbert_index_int(corner, 1) == h
+
+
+def test_hilbert_d1_identity(orc):
+    for B in [1, 3, 8]:
+        assert [orc.hilbert_index_int((v,), B) for v in range(1 << B)] == list(range(1 << B))
+
+
+def test_hilbert_top_level_is_gray_of_msbs(orc):
+    """Level B-1 of the key depends only on the coordinates' top bits (a sub-cube fact)."""
+    rng = np.random.default_rng(4)
+    d = 40
+    for _ in range(10):
+        v = rng.integers(0, 256, d, dtype=np.uint8)
+        w = v.copy()
+        w ^= rng.integers(0, 128, d, dtype=np.uint8)  # change only lower bits
+        kv, kw = orc.hilbert_index_int(v, 8), orc.hilbert_index_int(w, 8)
+        assert kv >> (7 * d) == kw >> (7 * d)
+        # and it is the Gray decode of the top bits (the B=1 curve of the top bits)
+        assert kv >> (7 * d) == orc.hilbert_index_int(list(v >> 7), 1)
+
+
+# ----------------------------------------------------------------- sort
+def test_sort_by_key_then_id(orc):
+    rng = np.random.default_rng(5)
+    codes = rng.integers(120, 136, (300, 6), dtype=np.uint8)
+    codes[50] = codes[7]  # exact duplicates
+    codes[200] = codes[7]
+    perm, refl = orc.curves(11, 1, 6)
+    keys = orc.tree_keys(codes, perm[0], refl[0])
+    order = orc.sort_keys(keys)
+    ref = sorted(range(300), key=lambda i: (tuple(int(w) for w in keys[i]), i))
+    assert order.tolist() == ref
+    # and the keys are the Skilling keys of the permuted/reflected codes
+    for p in [0, 7, 123]:
+        v = codes[p][perm[0]] ^ np.where(refl[0] == 1, 255, 0).astype(np.uint8)
+        assert (keys[p] == orc.hilbert_key(v, 8)).all()
+
+
+# ----------------------------------------------------------------- trie
+def _check_trie(orc, nodes, keys, order, codes, perm_t, refl_t, M):
+    N, d = codes.shape
+    W = keys.shape[1]
+    kint = [int("".join("%016x" % int(w) for w in keys[p]), 16) for p in range(N)]
+    nbits = 64 * W
+    leaves = []
+
+    def walk(idx, lo, hi, depth):
+        w0, w1 = int(nodes[idx, 0]), int(nodes[idx, 1])
+        if w1 >> 31:
+            assert w0 == lo and (w1 & 0x7FFFFFFF) == hi - lo
+            allsame = kint[order[lo]] == kint[order[hi - 1]]
+            assert hi - lo <= M or allsame
+            leaves.append((lo, hi))
+            return idx + 1
+        assert hi - lo > M
+        a, L, flip = w1 & 0xFFFF, (w1 >> 16) & 7, (w1 >> 19) & 1
+        bits = [(((codes[order[i], a] >> L) & 1) ^ flip) for i in range(lo, hi)]
+        # node test equals key bit b for every point of the range, and splits 0* 1+
+        x = kint[order[lo]] ^ kint[order[hi - 1]]
+        b = nbits - x.bit_length()
+        kb = [(kint[order[i]] >> (nbits - 1 - b)) & 1 for i in range(lo, hi)]
+        assert bits == kb
+        assert kb[0] == 0 and kb[-1] == 1 and kb == sorted(kb)
+        assert L == 7 - b // d
+        m = lo + kb.index(1)
+        nxt = walk(idx + 1, lo, m, depth + 1)
+        assert w0 == nxt  # right child follows the left subtree (pre-order)
+        return walk(w0, m, hi, depth + 1)
+
+    end = walk(0, 0, N, 0)
+    assert end == nodes.shape[0]
+    # leaves partition [0, N) in order
+    assert leaves[0][0] == 0 and leaves[-1][1] == N
+    assert all(a[1] == b[0] for a, b in zip(leaves, leaves[1:]))
+    return leaves
+
+
+@pytest.mark.parametrize("N,d,M,seed", [(500, 8, 10, 1), (700, 32, 25, 2), (300, 70, 7, 3),
+                                        (64, 5, 100, 4)])
+def test_trie_invariants_and_self_descent(orc, N, d, M, seed):
+    rng = np.random.default_rng(seed)
+    x = datagen.draw(datagen.centres(d, 4, seed, False), N, 0.1, seed + 9, np.float32)
+    e = orc.quant_exp(x)
+    codes = orc.quantize(x, e)
+    codes[N // 3] = codes[N // 2]  # a duplicate pair
+    perm, refl = orc.curves(seed, 2, d)
+    for t in range(2):
+        keys = orc.tree_keys(codes, perm[t], refl[t])
+        order = orc.sort_keys(keys)
+        nodes = orc.trie(keys, order, codes, perm[t], refl[t], M)
+        leaves = _check_trie(orc, nodes, keys, order, codes, perm[t], refl[t], M)
+        # every data point, used as a query, lands in the leaf that holds it
+        k1 = 2
+        ws = orc.window_starts(nodes, codes, N, k1)
+        rank = np.empty(N, np.int64)
+        rank[order] = np.arange(N)
+        for p in rng.choice(N, 60, replace=False):
+            lo, hi = next(l for l in leaves if l[0] <= rank[p] < l[1])
+            mid = (lo + hi) // 2
+            assert ws[p] == min(max(mid - k1 // 2, 0), max(0, N - k1))
+
+
+def test_trie_all_equal_is_one_leaf(orc):
+    codes = np.full((250, 6), 131, np.uint8)
+    perm, refl = orc.curves(1, 1, 6)
+    keys = orc.tree_keys(codes, perm[0], refl[0])
+    order = orc.sort_keys(keys)
+    nodes = orc.trie(keys, order, codes, perm[0], refl[0], 10)
+    assert nodes.tolist() == [[0, 0x80000000 | 250]]
+    assert order.tolist() == list(range(250))
+
+
+def test_window_start_clamping(orc):
+    nodes = np.array([[0, 0x80000000 | 10]], np.uint32)  # one leaf [0, 10)
+    q = np.zeros((1, 3), np.uint8)
+    assert orc.window_starts(nodes, q, 10, 4).tolist() == [3]  # mid 5 - 2
+    assert orc.window_starts(nodes, q, 10, 20).tolist() == [0]  # k1 > N
+    nodes = np.array([[5, 0x80000000 | 5]], np.uint32)  # leaf [5, 10), mid 7
+    assert orc.window_starts(nodes, q, 10, 8).tolist() == [2]  # 7-4=3 > N-k1=2 -> 2
+
+
+# ----------------------------------------------------------------- sketches
+def _splitmix_words(orc, seed, n):
+    # independent: drive the published generator through Python integers
+    M64 = (1 << 64) - 1
+    s, out = seed, []
+    for _ in range(n):
+        s = (s + 0x9E3779B97F4A7C15) & M64
+        z = s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        out.append(z ^ (z >> 31))
+    assert out[0] == orc.splitmix64(seed, 0)
+    return out
+
+
+def test_srp_against_matmul(orc):
+    d, n = 24, 40
+    x = datagen.mixture(n, d, 3, 0.2, 5, dtype=np.float16)
+    e = orc.quant_exp(x)
+    sk = orc.srp(x, e, 99)
+    words = _splitmix_words(orc, 99, (512 * d + 63) // 64)
+    bits = np.array([(words[b // 64] >> (b % 64)) & 1 for b in range(512 * d)], np.int64)
+    R = (2 * bits - 1).reshape(512, d)
+    xq = np.clip(np.rint(x.astype(np.float64) * 2.0 ** (e + 5)), -8191, 8191).astype(np.int64)
+    z = xq @ R.T
+    want_bits = (z >= 0).astype(np.uint8)
+    got_bits = np.unpackbits(sk.view(np.uint8), axis=1, bitorder="little")
+    assert (got_bits == want_bits).all()
+
+
+def test_srp_sign_symmetry_and_hamming(orc):
+    x = datagen.mixture(200, 64, 5, 0.1, 6, dtype=np.float32)
+    e = orc.quant_exp(np.concatenate([x, -x]))
+    a, b = orc.srp(x, e, 3), orc.srp(-x, e, 3)
+    # sketch(-x) is the complement except where a projection is exactly 0
+    ham = orc.hamming(a, b)
+    assert (ham >= 505).all() and (ham <= 512).mean() == 1.0
+    assert (orc.hamming(a, a) == 0).all()
+    h1 = orc.hamming(a[:50], a[50:100])
+    h2 = orc.hamming(a[50:100], a[:50])
+    assert (h1 == h2).all()
+
+
+# ----------------------------------------------------------------- Alg. 1 reductions
+def test_search_reduces_to_brute_force(orc):
+    """T=1, k1 >= N, k2 >= N, h=0: every point is a candidate, so S is the exact top-k."""
+    x, q = datagen.mixture(400, 16, 4, 0.1, 7, unit=False, dtype=np.float32, nq=30)
+    F = orc.build_forest(x, T=1, M=20, seed=1, sketch_seed=2)
+    r = orc.search(F, q, k1=400, k2=400, h=0, k=10)
+    bi, bs = orc.brute_force_ip(x, q, 10)
+    assert (r["c1n"] == 400).all()
+    assert (r["ids"] == bi).all()
+    assert np.allclose(r["scores"], bs, rtol=0, atol=1e-12)
+
+
+def test_search_set_algebra_tiny(orc):
+    """C1, C2 and E rebuilt with Python sets from the trees' windows."""
+    x, q = datagen.mixture(300, 12, 3, 0.1, 8, unit=False, dtype=np.float32, nq=12)
+    F = orc.build_forest(x, T=3, M=15, seed=3, sketch_seed=4)
+    k1, k2, h, k = 40, 25, 2, 5
+    r = orc.search(F, q, k1, k2, h, k)
+    N = 300
+    for i in range(q.shape[0]):
+        C1 = set()
+        for j, t in enumerate(F["trees"]):
+            s = int(r["winstart"][i, j])
+            C1 |= set(int(v) for v in F["tree_perm"][t][s:s + k1])
+        assert len(C1) == r["c1n"][i]
+        hm = {c: int(orc.hamming(r["qsk"][i], F["sk_pos"][c])) for c in C1}
+        C2 = sorted(C1, key=lambda c: (hm[c], c))[:k2]
+        assert r["c2"][i, :r["c2n"][i]].tolist() == C2
+        E = set()
+        for c in C2:
+            E |= set(range(max(0, c - h), min(N - 1, c + h) + 1))
+        assert len(E) == r["en"][i]
+        sc = {c: float(np.dot(q[i].astype(np.float64), x[F["pos2id"][c]].astype(np.float64)))
+              for c in E}
+        best = sorted(E, key=lambda c: (-sc[c], c))[:k]
+        assert r["ids"][i].tolist() == [int(F["pos2id"][c]) for c in best]
+
+
+def test_master_order_and_tree_positions(orc):
+    x = datagen.mixture(200, 8, 2, 0.2, 9, unit=False, dtype=np.float32)
+    F = orc.build_forest(x, T=2, M=10, seed=5, sketch_seed=6)
+    assert (F["tree_perm"][0] == np.arange(200)).all()  # tree 0 is the master order
+    assert (F["pos2id"][F["pos"]] == np.arange(200)).all()
+    assert sorted(F["tree_perm"][1].tolist()) == list(range(200))
+
+
+# ----------------------------------------------------------------- Alg. 2 reductions
+def test_graph_reduces_to_brute_force(orc):
+    x = datagen.mixture(300, 16, 4, 0.1, 10, dtype=np.float16)
+    orders, _ = orc.graph_orders(x, 2, 7)
+    rows = np.arange(300)
+    ids, sc, c1n = orc.graph_rows(x, orders, w=300, k=7, rows=rows)
+    bi, bs = orc.brute_force_graph(x, rows, 7)
+    assert (c1n == 299).all()
+    assert (ids == bi).all()
+    assert np.allclose(sc, bs, rtol=0, atol=1e-12)
+
+
+def test_graph_window_sets_tiny(orc):
+    x = datagen.mixture(120, 8, 3, 0.2, 11, dtype=np.float32)
+    orders, _ = orc.graph_orders(x, 3, 5)
+    w, k = 4, 3
+    rows = np.arange(0, 120, 7)
+    ids, sc, c1n = orc.graph_rows(x, orders, w, k, rows)
+    X = x.astype(np.float64)
+    for ri, p in enumerate(rows):
+        C1 = set()
+        for t in range(3):
+            i = int(np.where(orders[t] == p)[0][0])
+            C1 |= set(int(v) for v in orders[t][max(0, i - w):i + w + 1])
+        C1.discard(int(p))
+        assert len(C1) == c1n[ri]
+        cos = {c: X[p] @ X[c] / (np.linalg.norm(X[p]) * np.linalg.norm(X[c])) for c in C1}
+        assert ids[ri].tolist() == sorted(C1, key=lambda c: (-cos[c], c))[:k]
+
+
+def test_graph_prefilter_by_hamming(orc):
+    x = datagen.mixture(150, 16, 3, 0.2, 12, dtype=np.float16)
+    orders, e = orc.graph_orders(x, 2, 5)
+    sk = orc.srp(x, e, 13)
+    rows = np.arange(0, 150, 5)
+    w, k, k2 = 6, 4, 9
+    ids, sc, c1n = orc.graph_rows(x, orders, w, k, rows, k2=k2, sk=sk)
+    X = x.astype(np.float64)
+    for ri, p in enumerate(rows):
+        C1 = set()
+        for t in range(2):
+            i = int(np.where(orders[t] == p)[0][0])
+            C1 |= set(int(v) for v in orders[t][max(0, i - w):i + w + 1])
+        C1.discard(int(p))
+        hm = {c: int(orc.hamming(sk[p], sk[c])) for c in C1}
+        C2 = sorted(C1, key=lambda c: (hm[c], c))[:k2]
+        cos = {c: X[p] @ X[c] / (np.linalg.norm(X[p]) * np.linalg.norm(X[c])) for c in C2}
+        assert ids[ri].tolist() == sorted(C2, key=lambda c: (-cos[c], c))[:k]

@@ -1,0 +1,229 @@
+/*
+ * hf.h -- C ABI of the Hilbert-forest library (libhf.so) for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The method is the Hilbert forest of Imamura et al., "Hilbert Forest in the
+ * SISAP 2025 Indexing Challenge" (arXiv 2508.21682): points are ordered along
+ * Hilbert curves (Section 2), a forest of leaf-compressed Hilbert trees gives
+ * first-stage candidates for a whole query batch at once, binary sketches
+ * filter them by Hamming distance and vector distance picks the result
+ * (Section 3.1, Algorithm 1); a k-NN graph is built from windows along
+ * several Hilbert orders (Section 4.1, Algorithm 2).
+ *
+ * Conventions for every call:
+ *  - Pointers named *_dev are device pointers (HIP global memory) on the
+ *    current device; pointers named *_host are host pointers.  The caller
+ *    owns every input and output buffer.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued on it; device outputs are valid once the stream has completed.
+ *    Calls that must read a device value back (marked "synchronises") wait
+ *    for the stream before returning.
+ *  - Matrices are row-major and dense: X[i*d + j].
+ *  - Every call returns an hf_status and never throws.  On HF_ERR_INVALID_ARG
+ *    nothing is launched and outputs are untouched; the reason is available
+ *    from hf_last_error() (thread-local).
+ *  - Sizes: 1 <= N < 2^31, 1 <= d <= 4096.
+ */
+#ifndef HF_H
+#define HF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hf_status {
+  HF_OK = 0,
+  HF_ERR_INVALID_ARG = 1,     /* bad size, pointer or parameter */
+  HF_ERR_INVALID_INPUT = 2,   /* input data not finite */
+  HF_ERR_OOM = 3,             /* device allocation failed */
+  HF_ERR_DEVICE = 4,          /* a HIP call failed (text in hf_last_error) */
+  HF_ERR_INVALID_HANDLE = 5,  /* NULL or freed forest / hash handle */
+  HF_ERR_UNSUPPORTED = 6      /* parameters outside what the kernels implement */
+} hf_status;
+
+typedef enum hf_dtype { HF_F16 = 0, HF_F32 = 1 } hf_dtype;
+
+typedef enum hf_precision {
+  HF_PREC_FP32 = 0, /* score every expanded candidate in FP32 */
+  HF_PREC_BF16 = 1, /* score in BF16 on MFMA, FP32 rerank of survivors */
+  HF_PREC_FP8 = 2   /* score in FP8 e4m3 (per-row scale) on MFMA, FP32 rerank */
+} hf_precision;
+
+typedef enum hf_sketch_kind { HF_SKETCH_SRP = 0, HF_SKETCH_LEARNED = 1 } hf_sketch_kind;
+
+#define HF_QUANT_AUTO INT32_MIN
+#define HF_SKETCH_BITS 512
+#define HF_SKETCH_WORDS 8
+
+typedef struct hf_forest hf_forest;
+typedef struct hf_lhash hf_lhash;
+
+/* Build parameters (Section 3.1 "Key Hyperparameters": n trees; leaves of
+ * about M points).  struct_size must be sizeof(hf_forest_params). */
+typedef struct hf_forest_params {
+  uint32_t struct_size;
+  uint32_t n_trees;      /* n, 1..1024; tree 0's order is the master order */
+  uint32_t leaf_max;     /* M >= 1: ranges of at most M points become leaves */
+  int32_t quant_exp;     /* code exponent e, or HF_QUANT_AUTO (from the data) */
+  uint64_t seed;         /* seeds the curves (axis permutation + reflection) */
+  uint64_t sketch_seed;  /* seeds the SRP sketch projections */
+  uint32_t sketch;       /* hf_sketch_kind */
+  uint32_t reserved;
+  const hf_lhash* lhash; /* learned hash when sketch == HF_SKETCH_LEARNED */
+} hf_forest_params;
+
+/* Search parameters (Section 3.1: k1 per tree, k2 by sketches, h neighbours
+ * on each side in the master order).  struct_size = sizeof(hf_search_params). */
+typedef struct hf_search_params {
+  uint32_t struct_size;
+  uint32_t k;         /* results per query, 1..1024 */
+  uint32_t k1;        /* window per tree, >= 1 */
+  uint32_t k2;        /* kept after the Hamming filter, k <= k2 <= 4096 */
+  uint32_t h;         /* expansion half-width in master order */
+  uint32_t precision; /* hf_precision */
+  uint32_t survivors; /* low-precision survivors per query (0 = 4k) */
+  uint32_t reserved;
+} hf_search_params;
+
+/* Graph parameters (Section 4.1: n sorts, k1 candidates per point per sort
+ * read as the window +-w, k2 kept by sketches; k = 15 in the paper). */
+typedef struct hf_graph_params {
+  uint32_t struct_size;
+  uint32_t n_orders;   /* n, 1..4096 */
+  uint32_t window;     /* w: positions i-w..i+w of each order, 1..512, 2w < N */
+  uint32_t k;          /* neighbours per point, 1..32 */
+  uint32_t k2;         /* 0 = no sketch stage; else Hamming top-k2 first, k <= k2 <= 256 */
+  int32_t quant_exp;   /* code exponent e, or HF_QUANT_AUTO */
+  uint32_t sketch;     /* hf_sketch_kind (used when k2 > 0) */
+  uint64_t seed;       /* curves of the n orders */
+  uint64_t sketch_seed;
+  const hf_lhash* lhash;
+} hf_graph_params;
+
+/* ------------------------------------------------------------------ errors */
+const char* hf_status_str(hf_status s);
+/* Detail of the last failing call on this thread ("" if none). */
+const char* hf_last_error(void);
+
+/* ---------------------------------------------------------- building blocks */
+
+/* Curves of trees 0..T-1 (Algorithm 1 "randomized axis orders"; Algorithm 2
+ * "randomly permute coordinate axes"), computed on the host from one
+ * SplitMix64 stream seeded with `seed`: per tree a Fisher-Yates shuffle of the
+ * axes, then ceil(d/64) words whose bits (LSB first) mark reflected axes.
+ * perm_host[t*d + i] = data axis read by tree axis i; refl_host[t*d + i] = 1
+ * if that axis is reflected (x -> 255 - x).  Caller-owned, T*d entries each. */
+hf_status hf_curves(uint64_t seed, int32_t T, int32_t d, int32_t* perm_host, uint8_t* refl_host);
+
+/* Code exponent of a data set (the 8-bit fixed-point ordering codes): the
+ * largest e in [-8, 24] with 2^e*max(X) < 128 and 2^e*min(X) >= -128 (e = -8
+ * if none).  HF_ERR_INVALID_INPUT if X holds a non-finite value.
+ * Synchronises. */
+hf_status hf_quant_exp(const void* X_dev, hf_dtype dtype, int64_t n_elems, int32_t* e_out_host,
+                       void* stream);
+
+/* 8-bit ordering codes u = clamp(floor(x * 2^e) + 128, 0, 255), element-wise
+ * (the data's "vector quantization" step of Algorithms 1 and 2, here only
+ * used to order points). codes_dev: n_elems bytes. */
+hf_status hf_quantize(const void* X_dev, hf_dtype dtype, int64_t n_elems, int32_t e,
+                      uint8_t* codes_dev, void* stream);
+
+/* Hilbert sort (Section 2) of N points with codes codes_dev (N x d bytes)
+ * along curve `tree` of the stream seeded by `seed`: order_dev[i] = id of the
+ * i-th point by (Skilling Hilbert index of the permuted/reflected codes, id).
+ * split_dev (nullable, N-1 entries): split_dev[i] = index of the first key bit
+ * where points order[i] and order[i+1] differ (key bit b = level 7 - b/d,
+ * axis b%d, MSB first), or 0xFFFFFFFF if their keys are equal.
+ * Synchronises (the tie refinement reads counts back). */
+hf_status hf_hilbert_sort(const uint8_t* codes_dev, int64_t N, int32_t d, uint64_t seed,
+                          uint32_t tree, uint32_t* order_dev, uint32_t* split_dev, void* stream);
+
+/* 512-bit sign-of-random-projection sketches (the binary sketches compared by
+ * Hamming distance in Section 3.1; their construction is not given in the
+ * paper).  R[j][i] = +1 if bit j*d+i of the concatenated SplitMix64 outputs
+ * seeded by sketch_seed is 1, else -1; xq_i = clamp(rne(x_i*2^(e+5)), -8191,
+ * 8191); bit j = [sum_i R[j][i]*xq_i >= 0] stored in word j/64 at bit j%64.
+ * out_dev: N x 8 uint64 words. */
+hf_status hf_srp_sketch(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, int32_t e,
+                        uint64_t sketch_seed, uint64_t* out_dev, void* stream);
+
+/* ------------------------------------------------------------------ forest */
+
+/* Preprocessing of Algorithm 1: codes, master order (tree 0), sketches and
+ * vectors re-laid in master order, then n leaf-compressed Hilbert trees whose
+ * permutations hold master positions.  The forest keeps its own copies; X_dev
+ * is not retained.  *out receives a handle to free with hf_forest_free.
+ * Synchronises. */
+hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
+                          const hf_forest_params* params, void* stream, hf_forest** out);
+void hf_forest_free(hf_forest* f);
+
+typedef struct hf_forest_info {
+  int64_t N;
+  int32_t d, n_trees, leaf_max, quant_exp;
+  int32_t dtype;
+  int32_t device;
+  int64_t total_nodes;
+  int64_t device_bytes; /* bytes the forest holds on its device */
+} hf_forest_info;
+hf_status hf_forest_get_info(const hf_forest* f, hf_forest_info* info_host);
+
+/* Introspection (device outputs, caller-owned):
+ *  perm: N uint32 master positions of tree t in Hilbert order (tree 0 = 0..N-1);
+ *  nodes: the pre-order node records of tree t, 2 uint32 per node:
+ *    internal: {index of right child, a | L<<16 | flip<<19}: key bit of a point
+ *              = bit L of its code on data axis a, XOR flip; 0 = left child
+ *              (the next record), 1 = right child;
+ *    leaf:     {lo, 1<<31 | (hi - lo)}: positions [lo, hi) of the tree order.
+ *    Pass nodes_dev = NULL to get the count only.
+ *  pos2id: N uint32, original id of each master position;
+ *  sketches: N x 8 uint64 in master order. */
+hf_status hf_forest_perm(const hf_forest* f, uint32_t t, uint32_t* perm_dev, void* stream);
+hf_status hf_forest_nodes(const hf_forest* f, uint32_t t, uint32_t* nodes_dev, int64_t* count_host,
+                          void* stream);
+hf_status hf_forest_pos2id(const hf_forest* f, uint32_t* pos2id_dev, void* stream);
+hf_status hf_forest_sketches(const hf_forest* f, uint64_t* sk_dev, void* stream);
+
+/* Algorithm 1 for a batch of nq queries (same dtype as the data):
+ *  first stage: every query descends every tree (the collective "simulated
+ *    Hilbert sort"); its window is the k1 tree positions centred on the
+ *    midpoint of the leaf reached, shifted inside [0, N);
+ *  second stage: C2 = the k2 candidates of the union of the windows with the
+ *    smallest (Hamming distance of sketches, master position);
+ *  final: E = C2 expanded by h master positions on each side; S = top-k of E
+ *    by (inner product in FP32, descending; master position ascending).
+ * ids_dev: nq x k original ids (-1 past the end when |E| < k); scores_dev:
+ * nq x k FP32 inner products (-inf past the end). */
+hf_status hf_search(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64_t nq,
+                    const hf_search_params* params, int32_t* ids_dev, float* scores_dev,
+                    void* stream);
+
+/* hf_search plus the intermediate sets (all nullable, device, caller-owned):
+ * win_dev nq x n_trees window starts; c2_dev nq x k2 master positions in
+ * (Hamming, position) order, 0xFFFFFFFF past c2n; c2n_dev nq counts; en_dev
+ * nq sizes |E|. */
+hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64_t nq,
+                          const hf_search_params* params, int32_t* ids_dev, float* scores_dev,
+                          uint32_t* win_dev, uint32_t* c2_dev, int32_t* c2n_dev, int32_t* en_dev,
+                          void* stream);
+
+/* ------------------------------------------------------------------- graph */
+
+/* Algorithm 2: for each of n orders (Hilbert sort along seeded curve t),
+ * every point gets the points within +-w positions as candidates; the result
+ * is, per point, the top-k of the union of its candidates (self excluded) by
+ * (cosine similarity, descending; id ascending); with k2 > 0 the candidates
+ * are first cut to the k2 with the smallest (Hamming distance, id).
+ * ids_dev: N x k int32 original ids (-1 if fewer candidates); scores_dev:
+ * N x k FP32 cosines. fp16 data only.  Synchronises. */
+hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
+                       const hf_graph_params* params, int32_t* ids_dev, float* scores_dev,
+                       void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HF_H */

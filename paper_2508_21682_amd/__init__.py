@@ -1,0 +1,280 @@
+"""Python binding of libhf (Hilbert forest on MI355X).
+
+Argument marshalling only: every step runs in the HIP kernels of ``libhf.so``
+behind the C ABI declared in ``include/hf.h``.  Device buffers are torch
+tensors; the current torch stream is passed to the library.  Importing works
+without a GPU (for host-only calls such as :func:`curves`); device calls need
+the built library and a HIP device, and fail loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhf.so")
+
+HF_OK = 0
+HF_F16, HF_F32 = 0, 1
+HF_PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+HF_SKETCH_SRP, HF_SKETCH_LEARNED = 0, 1
+HF_QUANT_AUTO = -(2 ** 31)
+STATUS = {0: "ok", 1: "invalid argument", 2: "invalid input", 3: "out of memory", 4: "device error",
+          5: "invalid handle", 6: "unsupported"}
+
+EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_quantize",
+           "hf_hilbert_sort", "hf_srp_sketch", "hf_build_forest", "hf_forest_free",
+           "hf_forest_get_info", "hf_forest_perm", "hf_forest_nodes", "hf_forest_pos2id",
+           "hf_forest_sketches", "hf_search", "hf_search_debug", "hf_knn_graph"]
+
+
+class HFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class ForestParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_trees", C.c_uint32), ("leaf_max", C.c_uint32),
+                ("quant_exp", C.c_int32), ("seed", C.c_uint64), ("sketch_seed", C.c_uint64),
+                ("sketch", C.c_uint32), ("reserved", C.c_uint32), ("lhash", C.c_void_p)]
+
+
+class SearchParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("k", C.c_uint32), ("k1", C.c_uint32),
+                ("k2", C.c_uint32), ("h", C.c_uint32), ("precision", C.c_uint32),
+                ("survivors", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class GraphParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_orders", C.c_uint32), ("window", C.c_uint32),
+                ("k", C.c_uint32), ("k2", C.c_uint32), ("quant_exp", C.c_int32),
+                ("sketch", C.c_uint32), ("seed", C.c_uint64), ("sketch_seed", C.c_uint64),
+                ("lhash", C.c_void_p)]
+
+
+class ForestInfo(C.Structure):
+    _fields_ = [("N", C.c_int64), ("d", C.c_int32), ("n_trees", C.c_int32), ("leaf_max", C.c_int32),
+                ("quant_exp", C.c_int32), ("dtype", C.c_int32), ("device", C.c_int32),
+                ("total_nodes", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhf.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HFError(4, "libhf.so not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, u32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+        sig = {
+            "hf_status_str": (C.c_char_p, [C.c_int]),
+            "hf_last_error": (C.c_char_p, []),
+            "hf_curves": (C.c_int, [u64, i32, i32, P, P]),
+            "hf_quant_exp": (C.c_int, [P, C.c_int, i64, P, P]),
+            "hf_quantize": (C.c_int, [P, C.c_int, i64, i32, P, P]),
+            "hf_hilbert_sort": (C.c_int, [P, i64, i32, u64, u32, P, P, P]),
+            "hf_srp_sketch": (C.c_int, [P, C.c_int, i64, i32, i32, u64, P, P]),
+            "hf_build_forest": (C.c_int, [P, C.c_int, i64, i32, P, P, P]),
+            "hf_forest_free": (None, [P]),
+            "hf_forest_get_info": (C.c_int, [P, P]),
+            "hf_forest_perm": (C.c_int, [P, u32, P, P]),
+            "hf_forest_nodes": (C.c_int, [P, u32, P, P, P]),
+            "hf_forest_pos2id": (C.c_int, [P, P, P]),
+            "hf_forest_sketches": (C.c_int, [P, P, P]),
+            "hf_search": (C.c_int, [P, P, C.c_int, i64, P, P, P, P]),
+            "hf_search_debug": (C.c_int, [P, P, C.c_int, i64, P, P, P, P, P, P, P, P]),
+            "hf_knn_graph": (C.c_int, [P, C.c_int, i64, i32, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != HF_OK:
+        raise HFError(status, lib().hf_last_error().decode())
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype(x):
+    t = _torch()
+    if x.dtype == t.float16:
+        return HF_F16
+    if x.dtype == t.float32:
+        return HF_F32
+    raise TypeError("fp16 or fp32 tensors only, got %s" % x.dtype)
+
+
+def _dev(x):
+    t = _torch()
+    if not x.is_cuda:
+        raise ValueError("expected a device tensor")
+    return x.contiguous()
+
+
+def _empty(shape, dtype, like):
+    return _torch().empty(shape, dtype=dtype, device=like.device)
+
+
+# ---------------------------------------------------------------- building blocks
+def curves(seed: int, T: int, d: int):
+    perm = np.empty((T, d), np.int32)
+    refl = np.empty((T, d), np.uint8)
+    _check(lib().hf_curves(seed, T, d, perm.ctypes.data_as(C.c_void_p), refl.ctypes.data_as(C.c_void_p)))
+    return perm, refl
+
+
+def quant_exp(x) -> int:
+    x = _dev(x)
+    e = C.c_int32()
+    _check(lib().hf_quant_exp(_ptr(x), _dtype(x), x.numel(), C.byref(e), _stream()))
+    return int(e.value)
+
+
+def quantize(x, e: int):
+    x = _dev(x)
+    out = _empty(x.shape, _torch().uint8, x)
+    _check(lib().hf_quantize(_ptr(x), _dtype(x), x.numel(), e, _ptr(out), _stream()))
+    return out
+
+
+def hilbert_sort(codes, seed: int, tree: int = 0, with_split: bool = False):
+    """Ids in Hilbert order along curve `tree` (int32 tensor holding uint32 values)."""
+    codes = _dev(codes)
+    N, d = codes.shape
+    t = _torch()
+    order = _empty((N,), t.int32, codes)
+    split = _empty((max(N - 1, 1),), t.int32, codes) if with_split else None
+    _check(lib().hf_hilbert_sort(_ptr(codes), N, d, seed, tree, _ptr(order), _ptr(split), _stream()))
+    return (order, split[:N - 1]) if with_split else order
+
+
+def srp_sketch(x, e: int, sketch_seed: int):
+    x = _dev(x)
+    N, d = x.shape
+    out = _empty((N, 8), _torch().int64, x)
+    _check(lib().hf_srp_sketch(_ptr(x), _dtype(x), N, d, e, sketch_seed, _ptr(out), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- forest
+class Forest:
+    """Hilbert forest (Algorithm 1 preprocessing) owned by libhf on the current device."""
+
+    def __init__(self, x, n_trees: int, leaf_max: int = 100, seed: int = 0, sketch_seed: int = 0,
+                 quant_exp: int | None = None):
+        x = _dev(x)
+        p = ForestParams(C.sizeof(ForestParams), n_trees, leaf_max,
+                         HF_QUANT_AUTO if quant_exp is None else quant_exp, seed, sketch_seed,
+                         HF_SKETCH_SRP, 0, None)
+        h = C.c_void_p()
+        _check(lib().hf_build_forest(_ptr(x), _dtype(x), x.shape[0], x.shape[1], C.byref(p),
+                                     _stream(), C.byref(h)))
+        self._h = h
+        self.device = x.device
+        self.dtype = x.dtype
+        inf = ForestInfo()
+        _check(lib().hf_forest_get_info(self._h, C.byref(inf)))
+        self.info = {f: getattr(inf, f) for f, _ in ForestInfo._fields_}
+
+    def _like(self):
+        return _torch().empty(1, device=self.device)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().hf_forest_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def perm(self, t: int):
+        out = _empty((self.info["N"],), _torch().int32, self._like())
+        _check(lib().hf_forest_perm(self._h, t, _ptr(out), _stream()))
+        return out
+
+    def nodes(self, t: int):
+        n = C.c_int64()
+        _check(lib().hf_forest_nodes(self._h, t, None, C.byref(n), _stream()))
+        out = _empty((n.value, 2), _torch().int32, self._like())
+        _check(lib().hf_forest_nodes(self._h, t, _ptr(out), C.byref(n), _stream()))
+        return out
+
+    def pos2id(self):
+        out = _empty((self.info["N"],), _torch().int32, self._like())
+        _check(lib().hf_forest_pos2id(self._h, _ptr(out), _stream()))
+        return out
+
+    def sketches(self):
+        out = _empty((self.info["N"], 8), _torch().int64, self._like())
+        _check(lib().hf_forest_sketches(self._h, _ptr(out), _stream()))
+        return out
+
+    def _params(self, k, k1, k2, h, precision, survivors):
+        return SearchParams(C.sizeof(SearchParams), k, k1, k2, h, HF_PREC[precision], survivors, 0)
+
+    def search(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32", survivors: int = 0):
+        q = _dev(q)
+        t = _torch()
+        ids = _empty((q.shape[0], k), t.int32, q)
+        sc = _empty((q.shape[0], k), t.float32, q)
+        p = self._params(k, k1, k2, h, precision, survivors)
+        _check(lib().hf_search(self._h, _ptr(q), _dtype(q), q.shape[0], C.byref(p), _ptr(ids), _ptr(sc),
+                               _stream()))
+        return ids, sc
+
+    def search_debug(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32",
+                     survivors: int = 0):
+        q = _dev(q)
+        t = _torch()
+        nq = q.shape[0]
+        ids = _empty((nq, k), t.int32, q)
+        sc = _empty((nq, k), t.float32, q)
+        win = _empty((nq, self.info["n_trees"]), t.int32, q)
+        c2 = _empty((nq, k2), t.int32, q)
+        c2n = _empty((nq,), t.int32, q)
+        en = _empty((nq,), t.int32, q)
+        p = self._params(k, k1, k2, h, precision, survivors)
+        _check(lib().hf_search_debug(self._h, _ptr(q), _dtype(q), nq, C.byref(p), _ptr(ids), _ptr(sc),
+                                     _ptr(win), _ptr(c2), _ptr(c2n), _ptr(en), _stream()))
+        return dict(ids=ids, scores=sc, winstart=win, c2=c2, c2n=c2n, en=en)
+
+
+# ---------------------------------------------------------------- graph
+def knn_graph(x, n_orders: int, window: int, k: int, seed: int, k2: int = 0, sketch_seed: int = 0,
+              quant_exp: int | None = None):
+    x = _dev(x)
+    N, d = x.shape
+    t = _torch()
+    ids = _empty((N, k), t.int32, x)
+    sc = _empty((N, k), t.float32, x)
+    p = GraphParams(C.sizeof(GraphParams), n_orders, window, k, k2,
+                    HF_QUANT_AUTO if quant_exp is None else quant_exp, HF_SKETCH_SRP, seed, sketch_seed,
+                    None)
+    _check(lib().hf_knn_graph(_ptr(x), _dtype(x), N, d, C.byref(p), _ptr(ids), _ptr(sc), _stream()))
+    return ids, sc

@@ -1,0 +1,230 @@
+// k-NN graph from windows along several Hilbert orders (Section 4.1,
+// Algorithm 2).  Per order: Hilbert sort of all points, then a band kernel.
+//
+// Band kernel: a wavefront owns 16 consecutive positions of the order.  Their
+// rows (fp16, gathered through the order) stay in registers as the A operand
+// of v_mfma_f32_16x16x32_f16; the rows of each 16-position block within +-w
+// stream through as the B operand, so every MFMA tile is a 16x16 block of dot
+// products along the band.  Cosines (FP32 accumulate, FP32 norms) of the
+// pairs with 0 < |i-j| <= w are merged by the row's owner lane into that
+// point's top-k list (cosine desc, id asc), held in registers while the wave
+// runs and in HBM between orders.  A candidate already in the list is
+// skipped; one that was evicted earlier is evicted again (its score is
+// fixed), so the list stays the top-k of the union of all windows seen.
+#include <math.h>
+
+#include "hf_internal.h"
+
+namespace hf {
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+__global__ void k_norms(const __half* __restrict__ X, int64_t N, int d, float* __restrict__ nrm) {
+  int64_t p = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (p >= N) return;
+  float a = 0.f;
+  for (int i = __lane_id(); i < d; i += 64) {
+    float v = __half2float(X[p * d + i]);
+    a = fmaf(v, v, a);
+  }
+  for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m);
+  if (__lane_id() == 0) nrm[p] = sqrtf(a);
+}
+
+__global__ void k_init_lists(int32_t* __restrict__ ids, float* __restrict__ sc, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    ids[i] = -1;
+    sc[i] = -INFINITY;
+  }
+}
+
+__device__ __forceinline__ bool better(float s1, int32_t c1, float s2, int32_t c2) {
+  return s1 > s2 || (s1 == s2 && (uint32_t)c1 < (uint32_t)c2);
+}
+
+template <int KMAX>
+__device__ __forceinline__ void list_insert(float (&ls)[KMAX], int32_t (&li)[KMAX], int k, float s,
+                                            int32_t c) {
+  // reject if not better than the current k-th
+  float ws = -INFINITY;
+  int32_t wi = -1;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i)
+    if (i == k - 1) {
+      ws = ls[i];
+      wi = li[i];
+    }
+  if (!(wi < 0 || better(s, c, ws, wi))) return;
+  bool dup = false;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) dup |= (i < k) && (li[i] == c);
+  if (dup) return;
+  // shift worse entries down by one, place the candidate
+  bool placed = false;
+#pragma unroll
+  for (int i = KMAX - 1; i >= 1; --i) {
+    if (i < k && !placed) {
+      if (li[i - 1] < 0 || better(s, c, ls[i - 1], li[i - 1])) {
+        ls[i] = ls[i - 1];
+        li[i] = li[i - 1];
+      } else {
+        ls[i] = s;
+        li[i] = c;
+        placed = true;
+      }
+    }
+  }
+  if (!placed) {
+    ls[0] = s;
+    li[0] = c;
+  }
+}
+
+__device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t id, int d, int k0) {
+  if (id < 0 || k0 >= d) return (half8)(0);
+  uint4 raw = *(const uint4*)(X + id * d + k0);
+  return __builtin_bit_cast(half8, raw);
+}
+
+template <int KMAX, int KS>
+__global__ __launch_bounds__(256) void k_band(const __half* __restrict__ X, int64_t N, int d,
+                                              const uint32_t* __restrict__ order,
+                                              const float* __restrict__ nrm, int w, int k,
+                                              int32_t* __restrict__ gids, float* __restrict__ gsc) {
+  __shared__ float band[4][16][17];
+  const int wv = threadIdx.x / 64, l = __lane_id();
+  // every wave runs the whole loop (the block barriers below need all four)
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+  const int ri = l % 16, kg = l / 16;
+  const int64_t arow = r0 + ri < N ? (int64_t)order[r0 + ri] : -1;
+  half8 A[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) A[s] = load_row8(X, arow, d, 32 * s + 8 * kg);
+  // the owner lane (l < 16) holds the list of row r0 + l
+  float ls[KMAX];
+  int32_t li[KMAX];
+  const int64_t own = r0 + l;
+  const bool owner = l < 16 && own < N;
+  const int64_t own_id = owner ? (int64_t)order[own] : 0;
+  const float own_n = owner ? nrm[own_id] : 1.f;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    ls[i] = -INFINITY;
+    li[i] = -1;
+    if (owner && i < k) {
+      ls[i] = gsc[own_id * k + i];
+      li[i] = gids[own_id * k + i];
+    }
+  }
+  const int wr = (w + 15) / 16;
+  const int nblk = 1 + 2 * wr;
+  for (int cb = 0; cb < nblk; ++cb) {
+    const int64_t c0 = r0 + 16 * (int64_t)(cb - wr);
+    const int64_t cpos = c0 + ri;
+    const int64_t brow = (cpos >= 0 && cpos < N) ? (int64_t)order[cpos] : -1;
+    float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      half8 B = load_row8(X, brow, d, 32 * s + 8 * kg);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B, acc, 0, 0, 0);
+    }
+    // D layout: lane l holds rows 4*(l/16)+r, column l%16
+#pragma unroll
+    for (int r = 0; r < 4; ++r) band[wv][4 * kg + r][ri] = acc[r];
+    __syncthreads();
+    if (owner) {
+      for (int j = 0; j < 16; ++j) {
+        const int64_t cp = c0 + j;
+        const int64_t delta = cp - own;
+        if (delta == 0 || delta > w || -delta > w || cp < 0 || cp >= N) continue;
+        const int32_t cid = (int32_t)order[cp];
+        const float cs = band[wv][l][j] / (own_n * nrm[cid]);
+        list_insert<KMAX>(ls, li, k, cs, cid);
+      }
+    }
+    __syncthreads();
+  }
+  if (owner) {
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i)
+      if (i < k) {
+        gsc[own_id * k + i] = ls[i];
+        gids[own_id * k + i] = li[i];
+      }
+  }
+}
+
+unsigned grid_for(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, ceil_div(n, 256)));
+}
+
+template <int KMAX>
+hf_status launch_band(int ks, const __half* X, int64_t N, int d, const uint32_t* order,
+                      const float* nrm, int w, int k, int32_t* ids, float* sc, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(N, 64));
+  switch (ks) {
+#define HF_KS(n) \
+  case n: k_band<KMAX, n><<<grid, 256, 0, s>>>(X, N, d, order, nrm, w, k, ids, sc); break;
+    HF_KS(1) HF_KS(2) HF_KS(3) HF_KS(4) HF_KS(5) HF_KS(6) HF_KS(7) HF_KS(8) HF_KS(9) HF_KS(10)
+    HF_KS(11) HF_KS(12) HF_KS(13) HF_KS(14) HF_KS(15) HF_KS(16) HF_KS(20) HF_KS(24) HF_KS(32)
+#undef HF_KS
+    default:
+      set_error("graph band kernel: unsupported d");
+      return HF_ERR_UNSUPPORTED;
+  }
+  HF_LAUNCH_CHECK();
+  return HF_OK;
+}
+
+}  // namespace
+
+hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_graph_params& p, int e,
+                       int32_t* ids, float* scores, hipStream_t s) {
+  (void)dt;
+  if (p.k2 != 0) {
+    set_error("the sketch prefilter of the graph is not built");
+    return HF_ERR_UNSUPPORTED;
+  }
+  const __half* X = (const __half*)Xv;
+  int ks = (d + 31) / 32;
+  if (ks > 16) ks = ks <= 20 ? 20 : (ks <= 24 ? 24 : (ks <= 32 ? 32 : 0));
+  if (ks == 0) {
+    set_error("graph band kernel: d > 1024 not built");
+    return HF_ERR_UNSUPPORTED;
+  }
+  Workspace ws(s);
+  uint8_t* codes;
+  float* nrm;
+  uint32_t* order;
+  HF_TRY(ws.alloc(&codes, (size_t)(N * d)));
+  HF_TRY(ws.alloc(&nrm, (size_t)N));
+  HF_TRY(ws.alloc(&order, (size_t)N));
+  HF_TRY(quantize(X, HF_F16, N * d, e, codes, s));
+  k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, nrm);
+  k_init_lists<<<grid_for(N * p.k), 256, 0, s>>>(ids, scores, N * p.k);
+  HF_LAUNCH_CHECK();
+  const int T = (int)p.n_orders;
+  std::vector<int32_t> perm((size_t)T * d);
+  std::vector<uint8_t> refl((size_t)T * d);
+  make_curves(p.seed, T, d, perm.data(), refl.data());
+  int32_t* dperm;
+  uint8_t* drefl;
+  HF_TRY(ws.alloc(&dperm, (size_t)T * d));
+  HF_TRY(ws.alloc(&drefl, (size_t)T * d));
+  HIP_TRY(hipMemcpyAsync(dperm, perm.data(), 4 * (size_t)T * d, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(drefl, refl.data(), (size_t)T * d, hipMemcpyHostToDevice, s));
+  for (int t = 0; t < T; ++t) {
+    Workspace wt(s);
+    HF_TRY(hilbert_sort_dev(codes, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
+    if (p.k <= 16)
+      HF_TRY(launch_band<16>(ks, X, N, d, order, nrm, (int)p.window, (int)p.k, ids, scores, s));
+    else
+      HF_TRY(launch_band<32>(ks, X, N, d, order, nrm, (int)p.window, (int)p.k, ids, scores, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return HF_OK;
+}
+
+}  // namespace hf

@@ -1,0 +1,217 @@
+// Internal declarations of libhf: status handling, device helpers and the
+// host launchers each .hip file provides.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hf.h"
+
+namespace hf {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+struct Err {
+  hf_status s;
+};
+
+#define HF_TRY(expr)                                   \
+  do {                                                 \
+    hf_status _s = (expr);                             \
+    if (_s != HF_OK) return _s;                        \
+  } while (0)
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      ::hf::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),       \
+                      __FILE__, __LINE__);                                         \
+      return _e == hipErrorOutOfMemory ? HF_ERR_OOM : HF_ERR_DEVICE;               \
+    }                                                                              \
+  } while (0)
+
+#define HF_LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+#define HF_ARG(cond, ...)               \
+  do {                                  \
+    if (!(cond)) {                      \
+      ::hf::set_error(__VA_ARGS__);     \
+      return HF_ERR_INVALID_ARG;        \
+    }                                   \
+  } while (0)
+
+// ---------------------------------------------------------------- workspace
+// Device buffers owned by one call; freed (stream-ordered) on scope exit.
+struct Workspace {
+  hipStream_t stream;
+  std::vector<void*> ptrs;
+  explicit Workspace(hipStream_t s) : stream(s) {}
+  ~Workspace() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, stream);
+  }
+  template <class T>
+  hf_status alloc(T** out, size_t count) {
+    void* p = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess) {
+      set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      return HF_ERR_OOM;
+    }
+    ptrs.push_back(p);
+    *out = static_cast<T*>(p);
+    return HF_OK;
+  }
+};
+
+// ------------------------------------------------------------ device helpers
+constexpr int WAVE = 64;
+constexpr uint32_t NONE32 = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl(lo, src);
+  hi = __shfl(hi, src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl_xor(lo, m);
+  hi = __shfl_xor(hi, m);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+  for (int m = 32; m >= 1; m >>= 1) {
+    uint64_t o = shfl_xor_u64(v, m);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
+  for (int m = 32; m >= 1; m >>= 1) v |= shfl_xor_u64(v, m);
+  return v;
+}
+
+// Inclusive scan of uint32 over one wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  int l = __lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t o = __shfl_up(v, off);
+    if (l >= off) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan over a block of THREADS threads (one value each); `lds` holds
+// THREADS/64 + 1 words.  Returns the exclusive prefix, *total the sum.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total) {
+  constexpr int NW = THREADS / 64;
+  int w = threadIdx.x / 64, l = __lane_id();
+  uint32_t inc = wave_incl_scan(v);
+  if (l == 63) lds[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < NW; ++i) {
+      uint32_t t = lds[i];
+      lds[i] = run;
+      run += t;
+    }
+    lds[NW] = run;
+  }
+  __syncthreads();
+  uint32_t r = lds[w] + inc - v;
+  *total = lds[NW];
+  __syncthreads();
+  return r;
+}
+
+// float -> uint32 whose unsigned order is the float order (NaN-free input).
+__device__ __forceinline__ uint32_t float_to_ordered(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int bits_for(uint64_t max_value) {
+  int b = 0;
+  while (b < 64 && (max_value >> b) != 0) ++b;
+  return b;
+}
+
+// ---------------------------------------------------------------- launchers
+// hf_scan.hip
+hf_status excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev,
+                        Workspace& ws);
+// hf_radix.hip: stable LSD sort of (key, val) pairs on key bits [bit_lo, bit_hi).
+// Sorted pairs end in (*keys, *vals), which may be swapped with (alt_keys, alt_vals).
+hf_status radix_sort_pairs(uint64_t** keys, uint32_t** vals, uint64_t** alt_keys,
+                           uint32_t** alt_vals, int64_t n, int bit_lo, int bit_hi, Workspace& ws);
+// hf_quant.hip
+hf_status minmax(const void* X, hf_dtype dt, int64_t n, float* mn_host, float* mx_host,
+                 int* nonfinite_host, Workspace& ws);
+int choose_exp(float mn, float mx);
+hf_status quantize(const void* X, hf_dtype dt, int64_t n, int e, uint8_t* out, hipStream_t s);
+// hf_keys.hip
+hf_status key_chunks(const uint8_t* codes, int d, const int32_t* perm, const uint8_t* refl,
+                     const uint32_t* items, int64_t n_items, int chunk, uint64_t* out,
+                     hipStream_t s);
+hf_status node_tests(const uint8_t* codes, int d, const int32_t* perm, const uint8_t* refl,
+                     const uint32_t* points, const uint32_t* bits, int64_t n, uint32_t* out_w1,
+                     hipStream_t s);
+// hf_sort.hip: Hilbert sort with a curve already on the device.
+hf_status hilbert_sort_dev(const uint8_t* codes, int64_t N, int d, const int32_t* perm,
+                           const uint8_t* refl, uint32_t* order, uint32_t* split, Workspace& ws);
+// hf_trie.hip: pre-order trie records (2 words each) from a sorted order and its split bits.
+hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_t* perm,
+                     const uint8_t* refl, const uint32_t* order, const uint32_t* split,
+                     uint32_t** nodes_out, int64_t* n_nodes, Workspace& ws);
+// hf_sketch.hip
+hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64_t sketch_seed,
+                     uint64_t* out, Workspace& ws);
+// host helpers (hf_api.hip)
+void make_curves(uint64_t seed, int T, int d, int32_t* perm, uint8_t* refl);
+uint64_t splitmix64_next(uint64_t* state);
+
+}  // namespace hf
+
+// Forest handle.
+struct hf_forest {
+  uint32_t magic;
+  int device;
+  int64_t N;
+  int32_t d, T, M, e;
+  hf_dtype dtype;
+  uint64_t seed, sketch_seed;
+  void* X_pos;           // N x d rows in master order (dtype)
+  uint64_t* sk_pos;      // N x 8 sketch words in master order
+  uint32_t* pos2id;      // N
+  uint32_t* tree_perm;   // T x N master positions
+  uint32_t* nodes;       // all trees' records, 2 words per node
+  std::vector<int64_t> node_off;  // T+1 offsets (in nodes)
+  int32_t* curve_perm;   // T x d
+  uint8_t* curve_refl;   // T x d
+  int64_t device_bytes;
+};
+constexpr uint32_t HF_FOREST_MAGIC = 0x48464f52u;  // "HFOR"

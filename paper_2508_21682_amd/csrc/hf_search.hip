@@ -1,0 +1,614 @@
+// Search path of Algorithm 1 on the GPU:
+//   descend   - every (query, tree) pair walks its tree: the collective
+//               "simulated Hilbert sort" of the whole batch (first stage);
+//   ham       - streams each query's n*k1 window entries (duplicates
+//               included, as the paper counts them), gathers 64-byte
+//               sketches 16 bytes per lane and writes Hamming distances plus
+//               a per-query histogram;
+//   select    - the k2 smallest distinct (Hamming, master position) pairs:
+//               histogram -> largest bin range that fits in LDS -> collect,
+//               bitonic sort, drop duplicates; repeats on the next range
+//               (splitting a bin by position when it alone overflows);
+//   rerank    - C2 sorted by position, expanded by +-h into merged
+//               intervals (the expansion set E in increasing master order),
+//               FP32 inner products by 16-lane groups, radix select of the
+//               k best (score desc, position asc) and a final small sort.
+#include <math.h>
+
+#include "hf_internal.h"
+
+namespace hf {
+namespace {
+
+// ------------------------------------------------------------------ descend
+__global__ __launch_bounds__(256) void k_descend(const uint32_t* __restrict__ nodes,
+                                                 const int64_t* __restrict__ node_off,
+                                                 const uint8_t* __restrict__ qcodes, int64_t nq,
+                                                 int d, int T, int64_t N, int k1, int max_steps,
+                                                 uint32_t* __restrict__ win) {
+  int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int t = blockIdx.y;
+  if (q >= nq) return;
+  const uint32_t* nd = nodes + 2 * node_off[t];
+  const uint8_t* u = qcodes + q * d;
+  uint32_t idx = 0;
+  int64_t mid = 0;
+  for (int step = 0; step < max_steps; ++step) {
+    uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
+    if (r.y >> 31) {
+      mid = (int64_t)r.x + (int64_t)((r.y & 0x7FFFFFFFu) >> 1);
+      break;
+    }
+    uint32_t a = r.y & 0xFFFFu, L = (r.y >> 16) & 7u, flip = (r.y >> 19) & 1u;
+    uint32_t bit = ((u[a] >> L) & 1u) ^ flip;
+    idx = bit ? r.x : idx + 1u;
+  }
+  int64_t s = mid - k1 / 2, smax = N - k1 > 0 ? N - k1 : 0;
+  s = s < 0 ? 0 : (s > smax ? smax : s);
+  win[q * T + t] = (uint32_t)s;
+}
+
+// ---------------------------------------------------------------- ham + hist
+constexpr int HB = 513;  // Hamming values 0..512
+
+__global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_perm, int64_t N,
+                                             int T, int len, const uint32_t* __restrict__ win,
+                                             const uint64_t* __restrict__ sk,
+                                             const uint64_t* __restrict__ qsk,
+                                             uint16_t* __restrict__ ham,
+                                             uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[4][HB];
+  const int64_t q = blockIdx.x;
+  for (int i = threadIdx.x; i < 4 * HB; i += 256) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const int w = threadIdx.x / 64, grp = threadIdx.x / 4, qd = threadIdx.x & 3;
+  const uint64_t q0 = qsk[q * 8 + 2 * qd], q1 = qsk[q * 8 + 2 * qd + 1];
+  uint16_t* out = ham + q * (int64_t)T * len;
+  for (int t = 0; t < T; ++t) {
+    const uint32_t* P = tree_perm + (int64_t)t * N + win[q * T + t];
+    uint16_t* o = out + (int64_t)t * len;
+    for (int i0 = 0; i0 < len; i0 += 4 * 64) {
+      uint32_t pos[4];
+      ulonglong2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int i = i0 + u * 64 + grp;
+        pos[u] = i < len ? P[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int i = i0 + u * 64 + grp;
+        if (i < len) v[u] = *(const ulonglong2*)(sk + (int64_t)pos[u] * 8 + 2 * qd);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int i = i0 + u * 64 + grp;
+        uint32_t c = 0;
+        if (i < len) c = (uint32_t)(__popcll(v[u].x ^ q0) + __popcll(v[u].y ^ q1));
+        c += __shfl_xor(c, 1);
+        c += __shfl_xor(c, 2);
+        if (i < len && qd == 0) {
+          o[i] = (uint16_t)c;
+          atomicAdd(&h[w][c], 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < HB; i += 256)
+    hist[q * HB + i] = h[0][i] + h[1][i] + h[2][i] + h[3][i];
+}
+
+// ------------------------------------------------------------------ select
+constexpr int SEL_T = 1024;
+constexpr int CAP = 16384;
+constexpr int NBK = 1024;
+
+__device__ __forceinline__ void bitonic_u32(uint32_t* a, int n2) {
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        int ixj = i ^ j;
+        if (ixj > i) {
+          uint32_t x = a[i], y = a[ixj];
+          bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void bitonic_u64(uint64_t* a, int n2) {
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        int ixj = i ^ j;
+        if (ixj > i) {
+          uint64_t x = a[i], y = a[ixj];
+          bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ tree_perm,
+                                                  int64_t N, int T, int len,
+                                                  const uint32_t* __restrict__ win,
+                                                  const uint16_t* __restrict__ ham,
+                                                  const uint32_t* __restrict__ hist0, int k2,
+                                                  int pos_bits, uint32_t* __restrict__ c2,
+                                                  int32_t* __restrict__ c2n) {
+  __shared__ uint32_t keys[CAP];
+  __shared__ uint32_t hist[HB];
+  __shared__ uint32_t bk[NBK];
+  __shared__ uint32_t scan_tmp[SEL_T / 64 + 1];
+  __shared__ uint32_t s_cnt;
+  __shared__ int s_mode, s_hf, s_hb;
+  __shared__ uint32_t s_plo, s_pend, s_phi;
+
+  const int64_t q = blockIdx.x;
+  const uint16_t* hq = ham + q * (int64_t)T * len;
+  const uint32_t* wq = win + q * T;
+  const int HM = (int)((1ull << (32 - pos_bits)) - 1ull);
+  const uint32_t pmask = (uint32_t)((1ull << pos_bits) - 1ull);
+  int need = k2, outn = 0;
+  int lo_ham = 0;
+  uint32_t lo_pos = 0;
+  bool first = true;
+  const int64_t total = (int64_t)T * len;
+
+  while (need > 0) {
+    // histogram of the entries not yet consumed: (ham, pos) >= (lo_ham, lo_pos)
+    if (first) {
+      for (int i = threadIdx.x; i < HB; i += SEL_T) hist[i] = hist0[q * HB + i];
+      __syncthreads();
+    } else {
+      for (int i = threadIdx.x; i < HB; i += SEL_T) hist[i] = 0;
+      __syncthreads();
+      for (int t = 0; t < T; ++t) {
+        const uint32_t* P = tree_perm + (int64_t)t * N + wq[t];
+        for (int i = threadIdx.x; i < len; i += SEL_T) {
+          int hv = hq[(int64_t)t * len + i];
+          if (hv < lo_ham) continue;
+          if (hv == lo_ham && P[i] < lo_pos) continue;
+          atomicAdd(&hist[hv], 1u);
+        }
+      }
+      __syncthreads();
+    }
+    first = false;
+    if (threadIdx.x == 0) {
+      int hf = -1;
+      for (int h = lo_ham; h < HB; ++h)
+        if (hist[h]) {
+          hf = h;
+          break;
+        }
+      int hb = -1;
+      if (hf >= 0) {
+        uint32_t cum = 0;
+        for (int h = hf; h < HB && h - hf < HM; ++h) {
+          if (cum + hist[h] > (uint32_t)CAP) break;
+          cum += hist[h];
+          hb = h;
+        }
+      }
+      s_hf = hf;
+      s_hb = hb;
+      s_mode = hf < 0 ? 0 : (hb >= hf ? 1 : 2);
+      s_cnt = 0;
+      s_plo = (hf == lo_ham) ? lo_pos : 0u;
+      s_phi = (uint32_t)N;
+    }
+    __syncthreads();
+    const int mode = s_mode, hf = s_hf, hb = s_hb;
+    if (mode == 0) break;
+    if (mode == 2) {
+      // a single Hamming value overflows: narrow a position range until the
+      // first bucket prefix fits (a bucket of width 1 holds at most T entries)
+      for (;;) {
+        const uint32_t plo = s_plo, phi = s_phi;
+        const uint32_t width = (uint32_t)ceil_div((int64_t)(phi - plo), NBK);
+        for (int i = threadIdx.x; i < NBK; i += SEL_T) bk[i] = 0;
+        __syncthreads();
+        for (int t = 0; t < T; ++t) {
+          const uint32_t* P = tree_perm + (int64_t)t * N + wq[t];
+          for (int i = threadIdx.x; i < len; i += SEL_T) {
+            if (hq[(int64_t)t * len + i] != hf) continue;
+            uint32_t p = P[i];
+            if (p < plo || p >= phi) continue;
+            atomicAdd(&bk[(p - plo) / width], 1u);
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          uint32_t cum = 0;
+          int kb = -1;
+          for (int b = 0; b < NBK; ++b) {
+            if (cum + bk[b] > (uint32_t)CAP) break;
+            cum += bk[b];
+            kb = b;
+          }
+          if (kb >= 0) {
+            uint64_t e = (uint64_t)plo + (uint64_t)(kb + 1) * width;
+            s_pend = (uint32_t)(e < phi ? e : phi);
+            s_mode = 3;
+          } else {
+            s_phi = plo + width;
+          }
+        }
+        __syncthreads();
+        if (s_mode == 3) break;
+      }
+    }
+    // collect the chunk
+    const uint32_t plo = s_plo, pend = s_pend;
+    for (int t = 0; t < T; ++t) {
+      const uint32_t* P = tree_perm + (int64_t)t * N + wq[t];
+      for (int i = threadIdx.x; i < len; i += SEL_T) {
+        int hv = hq[(int64_t)t * len + i];
+        uint32_t p = P[i];
+        bool take;
+        uint32_t key;
+        if (mode == 1) {
+          take = hv >= hf && hv <= hb && !(hv == lo_ham && p < lo_pos);
+          key = ((uint32_t)(hv - hf) << pos_bits) | p;
+        } else {
+          take = hv == hf && p >= plo && p < pend;
+          key = p;
+        }
+        if (take) {
+          uint32_t slot = atomicAdd(&s_cnt, 1u);
+          keys[slot] = key;
+        }
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)s_cnt;
+    int n2 = 1;
+    while (n2 < cnt) n2 <<= 1;
+    for (int i = cnt + threadIdx.x; i < n2; i += SEL_T) keys[i] = NONE32;
+    __syncthreads();
+    bitonic_u32(keys, n2);
+    // distinct keys in order: each thread takes a contiguous run
+    const int per = (cnt + SEL_T - 1) / SEL_T;
+    const int a0 = threadIdx.x * per, a1 = min(cnt, a0 + per);
+    uint32_t mine = 0;
+    for (int i = a0; i < a1; ++i)
+      if (i == 0 || keys[i] != keys[i - 1]) ++mine;
+    uint32_t tot;
+    uint32_t r = block_excl_scan<SEL_T>(mine, scan_tmp, &tot);
+    for (int i = a0; i < a1; ++i)
+      if (i == 0 || keys[i] != keys[i - 1]) {
+        if ((int)r < need) {
+          uint32_t k = keys[i];
+          c2[q * k2 + outn + r] = mode == 1 ? (k & pmask) : k;
+        }
+        ++r;
+      }
+    int took = min(need, (int)tot);
+    need -= took;
+    outn += took;
+    if (mode == 1) {
+      lo_ham = hb + 1;
+      lo_pos = 0;
+      if (lo_ham >= HB) break;
+    } else {
+      lo_ham = hf;
+      lo_pos = pend;
+    }
+    __syncthreads();
+    if (total == 0) break;
+  }
+  for (int i = outn + threadIdx.x; i < k2; i += SEL_T) c2[q * k2 + i] = NONE32;
+  if (threadIdx.x == 0) c2n[q] = outn;
+}
+
+// ------------------------------------------------------------------ rerank
+constexpr int RR_T = 256;
+
+__device__ __forceinline__ float ordered_to_float(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+  return __uint_as_float(u);
+}
+
+// Position of expansion entry e: interval i with off[i] <= e < off[i+1].
+__device__ __forceinline__ uint32_t epos(const uint32_t* st, const uint32_t* off, int n2, uint32_t e) {
+  int lo = 0, hi = n2 - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return st[lo] + (e - off[lo]);
+}
+
+template <class T, bool VEC>
+__global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64_t N, int d,
+                                                 const T* __restrict__ Q,
+                                                 const uint32_t* __restrict__ c2,
+                                                 const int32_t* __restrict__ c2n, int k2, int h,
+                                                 int k, int k2p, int emax, int kp,
+                                                 const uint32_t* __restrict__ pos2id,
+                                                 int32_t* __restrict__ ids,
+                                                 float* __restrict__ scores,
+                                                 int32_t* __restrict__ en_out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* sq = (float*)smem;                                  // d
+  uint32_t* sc = (uint32_t*)(sq + ((d + 3) & ~3));           // k2p
+  uint32_t* st = sc + k2p;                                   // k2p
+  uint32_t* off = st + k2p;                                  // k2p + 1
+  uint32_t* ekey = off + k2p + 4;                            // emax
+  uint64_t* sel = (uint64_t*)(((uintptr_t)(ekey + emax) + 7) & ~(uintptr_t)7);  // kp
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t scan_tmp[RR_T / 64 + 1];
+  __shared__ uint32_t s_E, s_lt, s_eq_need, s_nsel;
+  __shared__ uint32_t s_prefix;
+
+  const int64_t q = blockIdx.x;
+  const int n2 = c2n[q];
+  for (int i = threadIdx.x; i < d; i += RR_T) {
+    if constexpr (sizeof(T) == 2)
+      sq[i] = __half2float(Q[q * d + i]);
+    else
+      sq[i] = Q[q * d + i];
+  }
+  for (int i = threadIdx.x; i < k2p; i += RR_T) sc[i] = i < n2 ? c2[q * k2 + i] : NONE32;
+  __syncthreads();
+  bitonic_u32(sc, k2p);
+  // merged intervals [max(0,r-h), min(N-1,r+h)] of the sorted positions
+  {
+    const int per = (n2 + RR_T - 1) / RR_T;
+    const int a0 = threadIdx.x * per, a1 = min(n2, a0 + per);
+    uint32_t mine = 0;
+    for (int i = a0; i < a1; ++i) {
+      int64_t r = sc[i];
+      int64_t a = r - h < 0 ? 0 : r - h, z = r + h > N - 1 ? N - 1 : r + h;
+      if (i > 0) {
+        int64_t pz = (int64_t)sc[i - 1] + h;
+        pz = pz > N - 1 ? N - 1 : pz;
+        if (a < pz + 1) a = pz + 1;
+      }
+      st[i] = (uint32_t)a;
+      off[i] = z >= a ? (uint32_t)(z - a + 1) : 0u;
+      mine += off[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan<RR_T>(mine, scan_tmp, &tot);
+    for (int i = a0; i < a1; ++i) {
+      uint32_t c = off[i];
+      off[i] = run;
+      run += c;
+    }
+    if (threadIdx.x == 0) {
+      off[n2] = tot;
+      s_E = tot;
+    }
+    __syncthreads();
+  }
+  const uint32_t E = s_E;
+  // scores: one row per 16-lane group
+  {
+    const int g = threadIdx.x / 16, gl = threadIdx.x % 16;
+    for (uint32_t e = g; e < E; e += RR_T / 16) {
+      uint32_t p = epos(st, off, n2, e);
+      const T* row = Xp + (int64_t)p * d;
+      float acc = 0.f;
+      if constexpr (VEC) {
+        constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
+        const int nch = d / EPC;
+        for (int c = gl; c < nch; c += 16) {
+          uint4 raw = *(const uint4*)(row + c * EPC);
+          const float* qq = sq + c * EPC;
+          if constexpr (sizeof(T) == 2) {
+            const __half2* hv = (const __half2*)&raw;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              float2 f = __half22float2(hv[j]);
+              acc = fmaf(f.x, qq[2 * j], acc);
+              acc = fmaf(f.y, qq[2 * j + 1], acc);
+            }
+          } else {
+            const float* fv = (const float*)&raw;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc = fmaf(fv[j], qq[j], acc);
+          }
+        }
+      } else {
+        for (int c = gl; c < d; c += 16) {
+          float xv;
+          if constexpr (sizeof(T) == 2)
+            xv = __half2float(row[c]);
+          else
+            xv = row[c];
+          acc = fmaf(xv, sq[c], acc);
+        }
+      }
+      acc += __shfl_xor(acc, 8);
+      acc += __shfl_xor(acc, 4);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 1);
+      if (gl == 0) ekey[e] = ~float_to_ordered(acc);  // ascending key = descending score
+    }
+  }
+  __syncthreads();
+  // radix select of the k-th smallest key
+  const uint32_t kk = (uint32_t)min<int64_t>(k, E);
+  if (threadIdx.x == 0) {
+    s_prefix = 0;
+    s_lt = 0;
+  }
+  __syncthreads();
+  uint32_t want = kk;  // rank (1-based) of the threshold key among keys with the prefix
+  for (int pass = 0; pass < 4 && kk > 0; ++pass) {
+    const int shift = 24 - 8 * pass;
+    const uint32_t pmask_hi = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
+    const uint32_t prefix = s_prefix;
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < E; e += RR_T) {
+      uint32_t key = ekey[e];
+      if ((key & pmask_hi) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t cum = 0;
+      int b = 0;
+      for (; b < 256; ++b) {
+        if (cum + hist[b] >= want) break;
+        cum += hist[b];
+      }
+      s_prefix = prefix | ((uint32_t)b << shift);
+      s_lt += cum;
+      want -= cum;
+    }
+    __syncthreads();
+    want = (want == kk && pass == 0) ? want : want;  // keep registers in sync below
+    if (threadIdx.x == 0) s_eq_need = want;
+    __syncthreads();
+    want = s_eq_need;
+  }
+  const uint32_t thr = s_prefix;
+  const uint32_t n_lt = s_lt;  // keys strictly below the threshold
+  // collect keys < thr, and the first (kk - n_lt) keys == thr in position order
+  if (threadIdx.x == 0) s_nsel = 0;
+  __syncthreads();
+  {
+    const int per = (int)((E + RR_T - 1) / RR_T);
+    const int a0 = threadIdx.x * per, a1 = min((int)E, a0 + per);
+    uint32_t myeq = 0;
+    for (int e = a0; e < a1; ++e) {
+      uint32_t key = ekey[e];
+      if (kk > 0 && key < thr) {
+        uint32_t slot = atomicAdd(&s_nsel, 1u);
+        sel[slot] = ((uint64_t)key << 32) | (uint32_t)e;
+      } else if (kk > 0 && key == thr) {
+        ++myeq;
+      }
+    }
+    uint32_t tot;
+    uint32_t r = block_excl_scan<RR_T>(myeq, scan_tmp, &tot);
+    const uint32_t need_eq = kk - n_lt;
+    for (int e = a0; e < a1; ++e) {
+      if (kk > 0 && ekey[e] == thr) {
+        if (r < need_eq) sel[n_lt + r] = ((uint64_t)thr << 32) | (uint32_t)e;
+        ++r;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = (int)kk + threadIdx.x; i < kp; i += RR_T) sel[i] = ~0ull;
+  __syncthreads();
+  bitonic_u64(sel, kp);
+  for (int i = threadIdx.x; i < k; i += RR_T) {
+    if (i < (int)kk) {
+      uint64_t v = sel[i];
+      uint32_t e = (uint32_t)v;
+      uint32_t p = epos(st, off, n2, e);
+      ids[q * k + i] = (int32_t)pos2id[p];
+      scores[q * k + i] = ordered_to_float(~(uint32_t)(v >> 32));
+    } else {
+      ids[q * k + i] = -1;
+      scores[q * k + i] = -INFINITY;
+    }
+  }
+  if (threadIdx.x == 0 && en_out) en_out[q] = (int32_t)E;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_search_params& p,
+                        int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
+                        int32_t* c2n_out, int32_t* en_out, hipStream_t s) {
+  Workspace ws(s);
+  const int64_t N = f->N;
+  const int d = f->d, T = f->T;
+  const int len = (int)std::min<int64_t>(p.k1, N);
+  const int k2 = (int)p.k2;
+  // query codes and sketches
+  uint8_t* qcodes;
+  uint64_t* qsk;
+  HF_TRY(ws.alloc(&qcodes, (size_t)(nq * d)));
+  HF_TRY(ws.alloc(&qsk, (size_t)(nq * 8)));
+  HF_TRY(quantize(Q, f->dtype, nq * d, f->e, qcodes, s));
+  HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws));
+  uint32_t* win = win_out;
+  if (!win) HF_TRY(ws.alloc(&win, (size_t)(nq * T)));
+  int64_t* doff;
+  HF_TRY(ws.alloc(&doff, (size_t)(T + 1)));
+  HIP_TRY(hipMemcpyAsync(doff, f->node_off.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
+  {
+    dim3 grid((unsigned)ceil_div(nq, 256), (unsigned)T);
+    k_descend<<<grid, 256, 0, s>>>(f->nodes, doff, qcodes, nq, d, T, N, (int)p.k1, 8 * d + 2, win);
+    HF_LAUNCH_CHECK();
+  }
+  // the second stage runs in batches of queries sized to bound scratch memory
+  const int64_t per_q = (int64_t)T * len;
+  int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1ll << 31) / (per_q * 2 + 1)));
+  uint16_t* ham;
+  uint32_t *hist, *c2 = c2_out;
+  int32_t* c2n = c2n_out;
+  HF_TRY(ws.alloc(&ham, (size_t)(batch * per_q)));
+  HF_TRY(ws.alloc(&hist, (size_t)(batch * HB)));
+  if (!c2) HF_TRY(ws.alloc(&c2, (size_t)(nq * k2)));
+  if (!c2n) HF_TRY(ws.alloc(&c2n, (size_t)nq));
+  const int pos_bits = std::max(1, bits_for((uint64_t)(N - 1)));
+  const int k2p = [&] { int v = 1; while (v < k2) v <<= 1; return v; }();
+  const int kp = [&] { int v = 1; while (v < (int)p.k) v <<= 1; return v; }();
+  const int64_t emax = std::min<int64_t>((int64_t)k2 * (2 * p.h + 1), N);
+  size_t smem = sizeof(float) * (((size_t)d + 3) & ~(size_t)3) + sizeof(uint32_t) * (3 * (size_t)k2p + 4) +
+                sizeof(uint32_t) * (size_t)emax + 8 + sizeof(uint64_t) * (size_t)kp;
+  if (smem > 160 * 1024) {
+    set_error("rerank needs %zu bytes of LDS (k2*(2h+1) too large)", smem);
+    return HF_ERR_UNSUPPORTED;
+  }
+  const size_t esz = f->dtype == HF_F16 ? 2 : 4;
+  const bool vec = ((size_t)d * esz) % 16 == 0;
+  auto rerank = [&](int64_t q0, int64_t nb) -> hf_status {
+    const void* Qb = (const char*)Q + q0 * d * esz;
+    if (f->dtype == HF_F16) {
+      auto kern = vec ? k_rerank<__half, true> : k_rerank<__half, false>;
+      if (smem > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+      kern<<<(unsigned)nb, RR_T, smem, s>>>((const __half*)f->X_pos, N, d, (const __half*)Qb,
+                                            c2 + q0 * k2, c2n + q0, k2, (int)p.h, (int)p.k, k2p,
+                                            (int)emax, kp, f->pos2id, ids + q0 * p.k,
+                                            scores + q0 * p.k, en_out ? en_out + q0 : nullptr);
+    } else {
+      auto kern = vec ? k_rerank<float, true> : k_rerank<float, false>;
+      if (smem > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+      kern<<<(unsigned)nb, RR_T, smem, s>>>((const float*)f->X_pos, N, d, (const float*)Qb,
+                                            c2 + q0 * k2, c2n + q0, k2, (int)p.h, (int)p.k, k2p,
+                                            (int)emax, kp, f->pos2id, ids + q0 * p.k,
+                                            scores + q0 * p.k, en_out ? en_out + q0 : nullptr);
+    }
+    HF_LAUNCH_CHECK();
+    return HF_OK;
+  };
+  for (int64_t q0 = 0; q0 < nq; q0 += batch) {
+    const int64_t nb = std::min(batch, nq - q0);
+    k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, f->sk_pos, qsk + q0 * 8,
+                                       ham, hist);
+    HF_LAUNCH_CHECK();
+    k_select<<<(unsigned)nb, SEL_T, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, ham, hist, k2,
+                                            pos_bits, c2 + q0 * k2, c2n + q0);
+    HF_LAUNCH_CHECK();
+    HF_TRY(rerank(q0, nb));
+  }
+  return HF_OK;
+}
+
+}  // namespace hf

@@ -1,0 +1,249 @@
+"""HIP path against the CPU oracle, through the C ABI.
+
+Integer outputs (codes, permutations, split bits, tree records, window
+starts, candidate lists, sketches) must be bit-identical.  FP32 scores must be
+within 1e-5 * |q| |x| of the oracle's FP64 scores; result ids may differ only
+where the oracle's FP64 scores are within that tolerance of the k-th score.
+"""
+import numpy as np
+import pytest
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def hf():
+    import torch
+
+    import paper_2508_21682_amd as hf
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    hf.lib()
+    return hf
+
+
+def dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def first_diff_bits(keys, order):
+    """Split bit of each adjacent pair in `order` from full oracle keys (NONE if equal)."""
+    a, b = keys[order[:-1]], keys[order[1:]]
+    x = a ^ b
+    out = np.full(len(order) - 1, 0xFFFFFFFF, np.uint64)
+    W = keys.shape[1]
+    for w in range(W - 1, -1, -1):  # the first differing word wins
+        nz = x[:, w] != 0
+        lz = np.zeros(nz.sum(), np.uint64)
+        v = x[nz, w].copy()
+        for sh in [32, 16, 8, 4, 2, 1]:
+            m = v < (np.uint64(1) << np.uint64(64 - sh))
+            lz[m] += np.uint64(sh)
+            v[m] <<= np.uint64(sh)
+        out[nz] = np.uint64(64 * w) + lz
+    return out.astype(np.uint32)
+
+
+def check_topk(gi, gs, oi, os_, x, q, k):
+    """Rank-wise scores within TOL; differing ids only at near-ties of the k-th score."""
+    assert gi.shape == oi.shape
+    fin = np.isfinite(os_)
+    assert (np.isfinite(gs) == fin).all()
+    assert np.abs(gs[fin] - os_[fin]).max() <= TOL
+    X = x.astype(np.float64)
+    Q = q.astype(np.float64)
+    bad = 0
+    for i in range(gi.shape[0]):
+        if (gi[i] == oi[i]).all():
+            continue
+        kth = os_[i, k - 1]
+        for c in set(gi[i].tolist()) ^ set(oi[i].tolist()):
+            if c < 0:
+                bad += 1
+                continue
+            s = float(Q[i] @ X[c])
+            if abs(s - kth) > TOL:
+                bad += 1
+    assert bad == 0, "%d ids differ beyond near-ties" % bad
+
+
+# ------------------------------------------------------------------ quantiser
+@pytest.mark.parametrize("dtype,d", [(np.float16, 384), (np.float32, 32), (np.float32, 7)])
+def test_quantize_parity(hf, orc, dtype, d):
+    x = datagen.mixture(3001, d, 5, 0.1, 21, unit=False, dtype=dtype)
+    x[0, :3] = np.array([0.0, -0.0, 2.0 ** -9], dtype)
+    xd = dev(x)
+    e = hf.quant_exp(xd)
+    assert e == orc.quant_exp(x)
+    assert (hf.quantize(xd, e).cpu().numpy() == orc.quantize(x, e)).all()
+    # queries outside the data range clamp
+    assert (hf.quantize(dev(x * 4), e).cpu().numpy() == orc.quantize(x * 4, e)).all()
+
+
+def test_quant_exp_rejects_nonfinite(hf):
+    x = np.ones((10, 4), np.float32)
+    x[3, 2] = np.nan
+    with pytest.raises(hf.HFError) as ei:
+        hf.quant_exp(dev(x))
+    assert ei.value.status == 2
+
+
+# ------------------------------------------------------------------ Hilbert sort
+SORT_CASES = [
+    # name, N, d, dtype, n_comp, sigma, unit, trees
+    ("c1-like", 10000, 32, np.float32, 16, 0.1, False, [0, 3]),
+    ("d384", 3000, 384, np.float16, 8, 0.05, True, [0, 1]),
+    ("d70", 2500, 70, np.float32, 4, 0.1, False, [2]),
+    ("d8-ties", 1500, 8, np.float32, 3, 0.3, False, [0, 1]),
+    ("d1", 500, 1, np.float32, 2, 0.5, False, [0]),
+    ("d2", 700, 2, np.float32, 2, 0.5, False, [0]),
+    ("d130-tight", 1200, 130, np.float16, 2, 0.002, True, [0]),
+]
+
+
+@pytest.mark.parametrize("case", SORT_CASES, ids=[c[0] for c in SORT_CASES])
+def test_hilbert_sort_parity(hf, orc, case):
+    name, N, d, dtype, nc, sigma, unit, trees = case
+    print("case", name, flush=True)
+    x = datagen.mixture(N, d, nc, sigma, 31 + N, unit=unit, dtype=dtype)
+    e = orc.quant_exp(x)
+    codes = orc.quantize(x, e)
+    codes[5] = codes[9]  # duplicates
+    codes[N - 1] = codes[9]
+    perm, refl = orc.curves(77, max(trees) + 1, d)
+    cd = dev(codes)
+    for t in trees:
+        keys = orc.tree_keys(codes, perm[t], refl[t])
+        want = orc.sort_keys(keys)
+        order, split = hf.hilbert_sort(cd, 77, t, with_split=True)
+        assert (u32(order) == want).all(), "tree %d order" % t
+        assert (u32(split) == first_diff_bits(keys, want)).all(), "tree %d split bits" % t
+
+
+def test_hilbert_sort_single_point(hf):
+    order = hf.hilbert_sort(dev(np.array([[3, 4, 5]], np.uint8)), 1, 0)
+    assert u32(order).tolist() == [0]
+
+
+# ------------------------------------------------------------------ sketches
+@pytest.mark.parametrize("dtype,d", [(np.float16, 384), (np.float32, 32), (np.float32, 70)])
+def test_srp_parity(hf, orc, dtype, d):
+    x = datagen.mixture(777, d, 3, 0.1, 41, dtype=dtype)
+    e = orc.quant_exp(x)
+    want = orc.srp(x, e, 1234)
+    got = hf.srp_sketch(dev(x), e, 1234).cpu().numpy().view(np.uint64)
+    assert (got == want).all()
+    # queries with larger values than the data clamp identically
+    want2 = orc.srp(x * 3, e, 1234)
+    got2 = hf.srp_sketch(dev(x * 3), e, 1234).cpu().numpy().view(np.uint64)
+    assert (got2 == want2).all()
+
+
+# ------------------------------------------------------------------ forest + search
+def _forest_case(hf, orc, x, q, T, M, seed, sk_seed, params):
+    F = orc.build_forest(x, T=T, M=M, seed=seed, sketch_seed=sk_seed)
+    fo = hf.Forest(dev(x), n_trees=T, leaf_max=M, seed=seed, sketch_seed=sk_seed)
+    assert fo.info["quant_exp"] == F["e"]
+    assert (u32(fo.pos2id()) == F["pos2id"]).all()
+    assert (fo.sketches().cpu().numpy().view(np.uint64) == F["sk_pos"]).all()
+    for t in range(T):
+        assert (u32(fo.perm(t)) == F["tree_perm"][t]).all(), "perm %d" % t
+        got = u32(fo.nodes(t)).reshape(-1, 2)
+        assert got.shape == F["nodes"][t].shape, "tree %d node count" % t
+        assert (got == F["nodes"][t]).all(), "tree %d records" % t
+    qd = dev(q)
+    for (k1, k2, h, k) in params:
+        print("search k1=%d k2=%d h=%d k=%d" % (k1, k2, h, k), flush=True)
+        want = orc.search(F, q, k1, k2, h, k)
+        r = fo.search_debug(qd, k, k1, k2, h)
+        assert (u32(r["winstart"]) == want["winstart"]).all()
+        assert (r["c2n"].cpu().numpy() == want["c2n"]).all()
+        assert (u32(r["c2"]) == want["c2"]).all()
+        assert (r["en"].cpu().numpy() == want["en"]).all()
+        check_topk(r["ids"].cpu().numpy(), r["scores"].cpu().numpy(), want["ids"], want["scores"], x, q, k)
+        ids2, sc2 = fo.search(qd, k, k1, k2, h)
+        assert (ids2.cpu().numpy() == r["ids"].cpu().numpy()).all()  # deterministic
+        assert (sc2.cpu().numpy() == r["scores"].cpu().numpy()).all()
+    fo.free()
+
+
+def test_forest_search_small_fp32(hf, orc):
+    """10,000 x 32 fp32 mixture, 8 trees, leaves of 100 points, 1,000 queries, k=10."""
+    w = datagen.WORKLOADS["search-10Kx32"]
+    x, q = datagen.mixture(w["n"], w["d"], w["n_comp"], w["sigma"], w["seed"], unit=w["unit"],
+                           dtype=np.float32, query_seed=w["query_seed"], nq=w["nq"])
+    _forest_case(hf, orc, x, q, T=8, M=100, seed=1, sk_seed=2,
+                 params=[(256, 64, 1, 10), (100, 10, 0, 10), (1000, 300, 3, 10)])
+
+
+def test_forest_search_fp16_d384(hf, orc):
+    x, q = datagen.mixture(20000, 384, 64, 0.05, 51, dtype=np.float16, query_seed=52, nq=150)
+    _forest_case(hf, orc, x, q, T=4, M=100, seed=5, sk_seed=6, params=[(300, 100, 2, 30)])
+
+
+def test_forest_edge_cases(hf, orc):
+    # N below k1 and below the leaf size: one leaf, the window is everything
+    x, q = datagen.mixture(150, 16, 3, 0.1, 61, unit=False, dtype=np.float32, nq=20)
+    _forest_case(hf, orc, x, q, T=3, M=200, seed=7, sk_seed=8,
+                 params=[(500, 150, 0, 10), (40, 20, 5, 20), (7, 5, 0, 5)])
+    # a ragged N with tiny leaves
+    x, q = datagen.mixture(1237, 24, 5, 0.1, 62, unit=False, dtype=np.float32, nq=33)
+    _forest_case(hf, orc, x, q, T=2, M=3, seed=9, sk_seed=10, params=[(17, 11, 1, 4)])
+
+
+def test_forest_duplicates_overflow_selection(hf, orc):
+    """All points identical: one oversized leaf, every candidate at Hamming 0,
+    more candidates than the selection buffer holds (position-split path)."""
+    N = 40000
+    x = np.tile(np.array([[0.25, -0.5, 0.125, 0.75, 0.0, -0.25, 0.5, 0.125]], np.float32), (N, 1))
+    q = x[:3].copy()
+    q[1, 0] = 0.3
+    _forest_case(hf, orc, x, q, T=2, M=100, seed=11, sk_seed=12, params=[(20000, 1000, 1, 20)])
+
+
+# ------------------------------------------------------------------ graph
+def _graph_case(hf, orc, x, n, w, k, seed, rows):
+    orders, _ = orc.graph_orders(x, n, seed)
+    oi, os_, _ = orc.graph_rows(x, orders, w, k, rows)
+    gi, gs = hf.knn_graph(dev(x), n, w, k, seed)
+    gi = gi.cpu().numpy()[rows]
+    gs = gs.cpu().numpy()[rows]
+    assert np.abs(gs - os_)[np.isfinite(os_)].max() <= TOL
+    assert (np.isfinite(os_) == np.isfinite(gs)).all()
+    X = x.astype(np.float64)
+    nrm = np.linalg.norm(X, axis=1)
+    bad = 0
+    for i, p in enumerate(rows):
+        if (gi[i] == oi[i]).all():
+            continue
+        kth = os_[i, k - 1]
+        for c in set(gi[i].tolist()) ^ set(oi[i].tolist()):
+            if c < 0:
+                bad += 1
+                continue
+            s = X[p] @ X[c] / (nrm[p] * nrm[c])
+            if abs(s - kth) > TOL:
+                bad += 1
+    assert bad == 0
+
+
+def test_graph_parity_d384(hf, orc):
+    x = datagen.mixture(20000, 384, 32, 0.05, 71, dtype=np.float16)
+    rows = np.random.default_rng(0).choice(20000, 1500, replace=False)
+    _graph_case(hf, orc, x, n=4, w=32, k=15, seed=3, rows=rows)
+
+
+def test_graph_parity_ragged(hf, orc):
+    x = datagen.mixture(333, 40, 4, 0.1, 72, dtype=np.float16)
+    _graph_case(hf, orc, x, n=3, w=21, k=7, seed=4, rows=np.arange(333))
+    x = datagen.mixture(100, 16, 2, 0.2, 73, dtype=np.float16)
+    _graph_case(hf, orc, x, n=2, w=49, k=20, seed=5, rows=np.arange(100))

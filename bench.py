@@ -1,0 +1,300 @@
+#!/usr/bin/env python
+"""Benchmark of the Hilbert-forest hot path on one MI355X.
+
+Default workload ("search-23Mx384"): 23,000,000 x 384 fp16 points of a seeded
+8,192-component Gaussian mixture on the sphere, 10,000 queries from the same
+mixture, a forest of 160 trees with leaves of at most 100 points, 512-bit SRP
+sketches, k = 30 by inner product with an FP32 rerank (the shape of the
+paper's Task 1).  One step = one hf_search call over the whole query batch
+(descent of every tree, Hamming filter, expansion, rerank); the forest is
+built once before timing, as the paper reports index construction apart
+from search.  The JSON line reports QPS, recall@30 against an exact GPU brute
+force, the roofline of the dominant kernel (HIP events on the library's
+stream over the timed region) and the CPU oracle timed on a bounded sample.
+
+"graph-3Mx384" times hf_knn_graph (Algorithm 2) on the 3M x 384 mixture.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench %.1fs]" % (time.time() - T0), *a, file=sys.stderr, flush=True)
+
+
+T0 = time.time()
+
+
+def ground_truth_ip(x, q, k, xchunk=1 << 20, qchunk=2500):
+    """Exact top-k by inner product (FP32 on the GPU), for recall only."""
+    import torch
+
+    nq = q.shape[0]
+    best_s = torch.full((nq, k), -float("inf"), device=x.device)
+    best_i = torch.zeros((nq, k), dtype=torch.int64, device=x.device)
+    qf = q.float()
+    for xs in range(0, x.shape[0], xchunk):
+        xf = x[xs:xs + xchunk].float()
+        for qs in range(0, nq, qchunk):
+            S = qf[qs:qs + qchunk] @ xf.T
+            s, i = torch.topk(S, k, dim=1)
+            cs = torch.cat([best_s[qs:qs + qchunk], s], 1)
+            ci = torch.cat([best_i[qs:qs + qchunk], i + xs], 1)
+            s2, j = torch.topk(cs, k, dim=1)
+            best_s[qs:qs + qchunk] = s2
+            best_i[qs:qs + qchunk] = torch.gather(ci, 1, j)
+            del S
+        del xf
+    return best_i
+
+
+def ground_truth_graph(x, rows, k, xchunk=1 << 20):
+    import torch
+
+    xn = x.float()
+    xn = xn / torch.linalg.vector_norm(xn, dim=1, keepdim=True)
+    q = xn[rows]
+    best_s = torch.full((rows.numel(), k), -float("inf"), device=x.device)
+    best_i = torch.zeros((rows.numel(), k), dtype=torch.int64, device=x.device)
+    for xs in range(0, x.shape[0], xchunk):
+        S = q @ xn[xs:xs + xchunk].T
+        self_hit = (rows >= xs) & (rows < xs + S.shape[1])
+        S[self_hit.nonzero().flatten(), (rows[self_hit] - xs)] = -float("inf")
+        s, i = torch.topk(S, k, dim=1)
+        cs = torch.cat([best_s, s], 1)
+        ci = torch.cat([best_i, i + xs], 1)
+        s2, j = torch.topk(cs, k, dim=1)
+        best_s, best_i = s2, torch.gather(ci, 1, j)
+    return best_i
+
+
+def recall(found, truth):
+    import torch
+
+    k = truth.shape[1]
+    hit = (found[:, :k].unsqueeze(2).long() == truth.unsqueeze(1)).any(2).sum().item()
+    return hit / float(truth.numel())
+
+
+def cpu_baseline_search(args):
+    """The oracle (untuned, all host threads) on a bounded sample of the search workload."""
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    n_s, t_s, nq_s = 100_000, 16, 5_000
+    w = datagen.WORKLOADS[args.workload]
+    comps = max(1, round(w["n_comp"] * n_s / w["n"]))
+    x, q = datagen.mixture(n_s, w["d"], comps, w["sigma"], w["seed"], dtype=np.float16,
+                           query_seed=w["query_seed"], nq=nq_s)
+    F = oracle.build_forest(x, T=t_s, M=args.leaf, seed=5, sketch_seed=6)
+    t = time.perf_counter()
+    oracle.search(F, q, args.k1, args.k2, args.h, args.k)
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": nq_s / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle search (Alg. 1 stages after the build) of %d queries on a %d x %d "
+                      "sample of the same mixture recipe (%d components), %d trees instead of %d, "
+                      "k1=%d k2=%d h=%d k=%d; %.2f s" % (nq_s, n_s, w["d"], comps, t_s, args.trees,
+                                                         args.k1, args.k2, args.h, args.k, dt)}
+
+
+def cpu_baseline_graph(args):
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    n_s, rows_s = 200_000, 20_000
+    w = datagen.WORKLOADS[args.workload]
+    comps = max(1, round(w["n_comp"] * n_s / w["n"]))
+    x = datagen.mixture(n_s, w["d"], comps, w["sigma"], w["seed"], dtype=np.float16)
+    t = time.perf_counter()
+    orders, _ = oracle.graph_orders(x, args.orders, 3)
+    rows = np.arange(rows_s)
+    oracle.graph_rows(x, orders, args.window, args.k, rows)
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # scale to the full job: orders are per point, rows are per point
+    est = dt * (w["n"] / n_s)
+    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": "oracle graph (%d orders, w=%d, k=%d) on a %d x %d sample: sorts of all %d points "
+                      "and candidate lists of %d rows took %.2f s; value = that time x %d/%d"
+                      % (args.orders, args.window, args.k, n_s, w["d"], n_s, rows_s, dt, w["n"], n_s)}
+
+
+def bench_search(args, hf, torch, ws):
+    import datagen
+
+    N = args.n or ws["n"]
+    nq = args.nq or ws["nq"]
+    d = ws["d"]
+    log("drawing %d x %d data and %d queries on the device" % (N, d, nq))
+    x = datagen.mixture_device(N, d, ws["n_comp"], ws["sigma"], ws["seed"], ws["unit"])
+    q = datagen.mixture_device(nq, d, ws["n_comp"], ws["sigma"], ws["seed"], ws["unit"],
+                               draw_seed=ws["query_seed"])
+    torch.cuda.synchronize()
+    log("building forest: %d trees, leaves <= %d" % (args.trees, args.leaf))
+    hf.timing_enable(True)
+    t = time.perf_counter()
+    forest = hf.Forest(x, n_trees=args.trees, leaf_max=args.leaf, seed=5, sketch_seed=6)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    build_stages = hf.timing_read()
+    log("forest built in %.2f s: %s" % (build_s, {k: round(v[0], 1) for k, v in build_stages.items()}))
+    log("ground truth (exact GPU brute force)")
+    gt = ground_truth_ip(x, q, args.k)
+    torch.cuda.synchronize()
+    sweep = []
+    if args.sweep:
+        for cfg in args.sweep.split(";"):
+            k1, k2, h = (int(v) for v in cfg.split(","))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ids, _ = forest.search(q, args.k, k1, k2, h)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            r = recall(ids, gt)
+            sweep.append({"k1": k1, "k2": k2, "h": h, "recall": r, "qps": nq / dt})
+            log("sweep k1=%d k2=%d h=%d: recall %.4f, %.0f QPS" % (k1, k2, h, r, nq / dt))
+            hf.timing_read()
+    for _ in range(args.warmup):
+        forest.search(q, args.k, args.k1, args.k2, args.h)
+    torch.cuda.synchronize()
+    hf.timing_read()
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        ids, sc = forest.search(q, args.k, args.k1, args.k2, args.h)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    stages = hf.timing_read()
+    hf.timing_enable(False)
+    rec = recall(ids, gt)
+    qps = nq * args.steps / dt
+    log("recall@%d %.4f, %.0f QPS, stages %s" % (args.k, rec, qps,
+                                                  {k: round(v[0] / args.steps, 2) for k, v in stages.items()}))
+    # roofline of the dominant kernel: the Hamming filter streams n*k1 window
+    # entries per query, each a 4-byte position read, a 64-byte sketch read and
+    # a 2-byte distance write (duplicates included, as the paper counts them)
+    T = args.trees
+    ln = min(args.k1, N)
+    ham_ms, ham_n = stages["hamming"]
+    per_launch_q = nq * args.steps / ham_n
+    bytes_launch = per_launch_q * (T * ln * 70 + T * 4 + 64 + 513 * 4)
+    achieved = bytes_launch / (ham_ms / ham_n * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_ham", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": bytes_launch, "ms_per_launch": ham_ms / ham_n}
+    res = {"metric": "QPS @recall@30>=0.7 (23Mx384)", "value": qps, "unit": "queries/s",
+           "ms_per_step": dt * 1e3 / args.steps, "recall": rec, "higher_is_better": True,
+           "config": {"workload": args.workload, "n": N, "d": d, "queries": nq, "trees": T,
+                      "leaf_max": args.leaf, "k": args.k, "k1": args.k1, "k2": args.k2, "h": args.h,
+                      "sketch_bits": 512, "rerank": "fp32"},
+           "build_s": build_s, "roofline": roof,
+           "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
+    if sweep:
+        res["sweep"] = sweep
+    forest.free()
+    return res
+
+
+def bench_graph(args, hf, torch, ws):
+    import datagen
+
+    N = args.n or ws["n"]
+    d = ws["d"]
+    log("drawing %d x %d data on the device" % (N, d))
+    x = datagen.mixture_device(N, d, ws["n_comp"], ws["sigma"], ws["seed"], ws["unit"])
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        hf.knn_graph(x, args.orders, args.window, args.k, 3)
+    torch.cuda.synchronize()
+    hf.timing_enable(True)
+    hf.timing_read()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        ids, sc = hf.knn_graph(x, args.orders, args.window, args.k, 3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    stages = hf.timing_read()
+    hf.timing_enable(False)
+    rows = torch.randperm(N, generator=torch.Generator(device="cpu").manual_seed(4))[:10000].to(x.device)
+    gt = ground_truth_graph(x, rows, args.k)
+    rec = recall(ids[rows], gt)
+    log("graph %.3f s, recall %.4f, stages %s" % (dt / args.steps, rec,
+                                                   {k: round(v[0] / args.steps, 2) for k, v in stages.items()}))
+    band_ms, band_n = stages["graph_band"]
+    # per band launch: every position reads its row once (768 B) plus its
+    # neighbours' rows through the cache, reads and writes its top-k list
+    bytes_launch = N * (d * 2 + 4 + 4 + args.k * 8 * 2)
+    achieved = bytes_launch / (band_ms / band_n * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_band", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": bytes_launch,
+            "ms_per_launch": band_ms / band_n}
+    return {"metric": "kNN-graph build s (3Mx384, k=15)", "value": dt / args.steps, "unit": "s",
+            "ms_per_step": dt * 1e3 / args.steps, "recall": rec, "higher_is_better": False,
+            "config": {"workload": args.workload, "n": N, "d": d, "orders": args.orders,
+                       "window": args.window, "k": args.k}, "roofline": roof,
+            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="search-23Mx384", choices=["search-23Mx384", "graph-3Mx384"])
+    ap.add_argument("--n", type=int, default=None, help="override N (development runs only)")
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--trees", type=int, default=160)
+    ap.add_argument("--leaf", type=int, default=100)
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--k1", type=int, default=1100)
+    ap.add_argument("--k2", type=int, default=310)
+    ap.add_argument("--h", type=int, default=2)
+    ap.add_argument("--orders", type=int, default=32)
+    ap.add_argument("--window", type=int, default=32)
+    ap.add_argument("--sweep", default=None, help="extra search configs 'k1,k2,h;k1,k2,h'")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: multi-GPU runs are not part of this build (got --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.k is None:
+        args.k = 30 if args.workload.startswith("search") else 15
+    import torch
+
+    import datagen
+    import paper_2508_21682_amd as hf
+
+    hf.lib()
+    ws = datagen.WORKLOADS[args.workload]
+    if args.workload.startswith("search"):
+        res = bench_search(args, hf, torch, ws)
+    else:
+        res = bench_graph(args, hf, torch, ws)
+    res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f16", "data": "synthetic"})
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        res["cpu_baseline"] = (cpu_baseline_search if args.workload.startswith("search")
+                               else cpu_baseline_graph)(args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -56,17 +56,19 @@ def mixture(n: int, d: int, n_comp: int, sigma: float, seed: int, unit: bool = T
 
 
 def mixture_device(n: int, d: int, n_comp: int, sigma: float, seed: int, unit: bool = True,
-                   device="cuda", chunk: int = 1 << 20, out=None):
+                   device="cuda", chunk: int = 1 << 20, out=None, draw_seed: int | None = None):
     """Large mixture drawn on the device with torch's generator (fp16 result).
 
-    Centres come from the host generator (same as :func:`centres`); component
-    choices and noise come from ``torch.Generator(device).manual_seed(seed)``.
+    Centres come from the host generator seeded by ``seed`` (same as
+    :func:`centres`); component choices and noise come from
+    ``torch.Generator(device).manual_seed(draw_seed or seed)`` (queries use
+    the data's ``seed`` for the centres and their own ``draw_seed``).
     """
     import torch
 
     c = torch.from_numpy(centres(d, n_comp, seed, unit)).to(device=device, dtype=torch.float32)
     g = torch.Generator(device=device)
-    g.manual_seed(int(seed))
+    g.manual_seed(int(seed if draw_seed is None else draw_seed))
     if out is None:
         out = torch.empty((n, d), dtype=torch.float16, device=device)
     for s in range(0, n, chunk):

@@ -210,6 +210,20 @@ hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype,
                           uint32_t* win_dev, uint32_t* c2_dev, int32_t* c2n_dev, int32_t* en_dev,
                           void* stream);
 
+/* ------------------------------------------------------------------ timing */
+
+/* Per-kernel timing with hipEvents recorded on the caller's stream around
+ * each launch of the hot kernels (thread-local; off by default).  Stages:
+ * 0 query codes, 1 query sketches, 2 descend, 3 hamming, 4 select, 5 rerank,
+ * 6 graph sort, 7 graph band, 8 build sort, 9 build trie, 10 build sketch,
+ * 11 lowprec score. */
+#define HF_N_STAGES 12
+hf_status hf_timing_enable(int32_t on);
+/* Waits for the recorded events, writes the summed milliseconds and launch
+ * counts of every stage since the last read (arrays of HF_N_STAGES), clears. */
+hf_status hf_timing_read(float* ms_host, int32_t* launches_host);
+const char* hf_timing_stage_name(int32_t stage);
+
 /* ------------------------------------------------------------------- graph */
 
 /* Algorithm 2: for each of n orders (Hilbert sort along seeded curve t),

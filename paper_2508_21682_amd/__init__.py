@@ -27,7 +27,9 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "invalid input", 3: "out of memory"
 EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_quantize",
            "hf_hilbert_sort", "hf_srp_sketch", "hf_build_forest", "hf_forest_free",
            "hf_forest_get_info", "hf_forest_perm", "hf_forest_nodes", "hf_forest_pos2id",
-           "hf_forest_sketches", "hf_search", "hf_search_debug", "hf_knn_graph"]
+           "hf_forest_sketches", "hf_search", "hf_search_debug", "hf_knn_graph",
+           "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name"]
+N_STAGES = 12
 
 
 class HFError(RuntimeError):
@@ -90,6 +92,9 @@ def lib():
             "hf_search": (C.c_int, [P, P, C.c_int, i64, P, P, P, P]),
             "hf_search_debug": (C.c_int, [P, P, C.c_int, i64, P, P, P, P, P, P, P, P]),
             "hf_knn_graph": (C.c_int, [P, C.c_int, i64, i32, P, P, P, P]),
+            "hf_timing_enable": (C.c_int, [i32]),
+            "hf_timing_read": (C.c_int, [P, P]),
+            "hf_timing_stage_name": (C.c_char_p, [i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -177,6 +182,19 @@ def srp_sketch(x, e: int, sketch_seed: int):
     out = _empty((N, 8), _torch().int64, x)
     _check(lib().hf_srp_sketch(_ptr(x), _dtype(x), N, d, e, sketch_seed, _ptr(out), _stream()))
     return out
+
+
+def timing_enable(on: bool = True):
+    _check(lib().hf_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """{stage: (total ms, launches)} of the kernels timed since the last read."""
+    ms = (C.c_float * N_STAGES)()
+    n = (C.c_int32 * N_STAGES)()
+    _check(lib().hf_timing_read(ms, n))
+    return {lib().hf_timing_stage_name(i).decode(): (float(ms[i]), int(n[i])) for i in range(N_STAGES)
+            if n[i] > 0}
 
 
 # ---------------------------------------------------------------- forest

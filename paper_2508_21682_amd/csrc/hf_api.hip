@@ -2,6 +2,7 @@
 // (Algorithm 1 preprocessing), introspection and error reporting.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 
 #include <algorithm>
 
@@ -20,6 +21,37 @@ void set_error(const char* fmt, ...) {
   g_err = buf;
 }
 void clear_error() { g_err.clear(); }
+
+// ------------------------------------------------------------------ timing
+namespace {
+struct TimedSpan {
+  int stage;
+  hipEvent_t a, b;
+};
+thread_local bool t_on = false;
+thread_local std::vector<TimedSpan> t_spans;
+thread_local std::vector<hipEvent_t> t_open(ST_COUNT, nullptr);
+const char* kStageNames[ST_COUNT] = {"query_codes", "query_sketch", "descend", "hamming", "select",
+                                     "rerank", "graph_sort", "graph_band", "build_sort", "build_trie",
+                                     "build_sketch", "lowprec_score"};
+}  // namespace
+
+bool timing_on() { return t_on; }
+
+void timing_mark(int stage, bool begin, hipStream_t s) {
+  if (!t_on) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, s);
+  if (begin) {
+    t_open[stage] = e;
+  } else if (t_open[stage]) {
+    t_spans.push_back({stage, t_open[stage], e});
+    t_open[stage] = nullptr;
+  } else {
+    (void)hipEventDestroy(e);
+  }
+}
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014).
 uint64_t splitmix64_next(uint64_t* state) {
@@ -148,6 +180,35 @@ const char* hf_status_str(hf_status s) {
 }
 
 const char* hf_last_error(void) { return g_err.c_str(); }
+
+hf_status hf_timing_enable(int32_t on) {
+  t_on = on != 0;
+  return HF_OK;
+}
+
+hf_status hf_timing_read(float* ms_host, int32_t* launches_host) {
+  clear_error();
+  HF_ARG(ms_host && launches_host, "null pointer");
+  for (int i = 0; i < ST_COUNT; ++i) {
+    ms_host[i] = 0.f;
+    launches_host[i] = 0;
+  }
+  for (auto& sp : t_spans) {
+    float ms = 0.f;
+    HIP_TRY(hipEventSynchronize(sp.b));
+    HIP_TRY(hipEventElapsedTime(&ms, sp.a, sp.b));
+    ms_host[sp.stage] += ms;
+    launches_host[sp.stage] += 1;
+    (void)hipEventDestroy(sp.a);
+    (void)hipEventDestroy(sp.b);
+  }
+  t_spans.clear();
+  return HF_OK;
+}
+
+const char* hf_timing_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < ST_COUNT) ? kStageNames[stage] : "";
+}
 
 hf_status hf_curves(uint64_t seed, int32_t T, int32_t d, int32_t* perm_host, uint8_t* refl_host) {
   clear_error();
@@ -281,15 +342,26 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
         if (p) (void)hipFree(p);
     }
   } ng{tnodes};
+  const bool progress = getenv("HF_PROGRESS") != nullptr;
   for (int t = 0; t < T; ++t) {
+    if (progress && (t % 16 == 0 || t == T - 1)) {
+      fprintf(stderr, "[libhf] building tree %d/%d\n", t + 1, T);
+      fflush(stderr);
+    }
     Workspace wt(s);
     uint32_t *order, *split;
     HF_TRY(wt.alloc(&order, N));
     HF_TRY(wt.alloc(&split, N));
     const int32_t* pt = f->curve_perm + (size_t)t * d;
     const uint8_t* rt = f->curve_refl + (size_t)t * d;
-    HF_TRY(hilbert_sort_dev(codes, N, d, pt, rt, order, split, wt));
-    HF_TRY(build_trie(codes, N, d, f->M, pt, rt, order, split, &tnodes[t], &tcount[t], wt));
+    {
+      StageTimer tm(ST_BSORT, s);
+      HF_TRY(hilbert_sort_dev(codes, N, d, pt, rt, order, split, wt));
+    }
+    {
+      StageTimer tm(ST_BTRIE, s);
+      HF_TRY(build_trie(codes, N, d, f->M, pt, rt, order, split, &tnodes[t], &tcount[t], wt));
+    }
     uint32_t* tp = f->tree_perm + (size_t)t * N;
     if (t == 0) {
       HIP_TRY(hipMemcpyAsync(f->pos2id, order, 4 * N, hipMemcpyDeviceToDevice, s));
@@ -309,7 +381,10 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
                                                                (int64_t)(esz * d), f->pos2id, N,
                                                                (unsigned char*)f->X_pos);
   HF_LAUNCH_CHECK();
-  HF_TRY(srp_sketch(f->X_pos, dtype, N, d, e, params->sketch_seed, f->sk_pos, ws));
+  {
+    StageTimer tm(ST_BSKETCH, s);
+    HF_TRY(srp_sketch(f->X_pos, dtype, N, d, e, params->sketch_seed, f->sk_pos, ws));
+  }
   HIP_TRY(hipStreamSynchronize(s));
   f->device_bytes = (int64_t)(esz * N * d + 64 * N + 4 * N + 4 * (size_t)T * N +
                               8 * (size_t)f->node_off[T] + 5 * (size_t)T * d);

@@ -217,7 +217,11 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   HIP_TRY(hipMemcpyAsync(drefl, refl.data(), (size_t)T * d, hipMemcpyHostToDevice, s));
   for (int t = 0; t < T; ++t) {
     Workspace wt(s);
-    HF_TRY(hilbert_sort_dev(codes, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
+    {
+      StageTimer tm(ST_GSORT, s);
+      HF_TRY(hilbert_sort_dev(codes, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
+    }
+    StageTimer tm(ST_GBAND, s);
     if (p.k <= 16)
       HF_TRY(launch_band<16>(ks, X, N, d, order, nrm, (int)p.window, (int)p.k, ids, scores, s));
     else

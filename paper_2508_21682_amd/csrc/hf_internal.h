@@ -190,6 +190,17 @@ hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_
 // hf_sketch.hip
 hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64_t sketch_seed,
                      uint64_t* out, Workspace& ws);
+// stage timing (hf_api.hip): events around a launch when timing is on
+enum Stage { ST_QCODES = 0, ST_QSKETCH, ST_DESCEND, ST_HAM, ST_SELECT, ST_RERANK, ST_GSORT, ST_GBAND,
+             ST_BSORT, ST_BTRIE, ST_BSKETCH, ST_LOWPREC, ST_COUNT };
+bool timing_on();
+void timing_mark(int stage, bool begin, hipStream_t s);
+struct StageTimer {
+  int st;
+  hipStream_t s;
+  StageTimer(int stage, hipStream_t stream) : st(stage), s(stream) { timing_mark(st, true, s); }
+  ~StageTimer() { timing_mark(st, false, s); }
+};
 // host helpers (hf_api.hip)
 void make_curves(uint64_t seed, int T, int d, int32_t* perm, uint8_t* refl);
 uint64_t splitmix64_next(uint64_t* state);

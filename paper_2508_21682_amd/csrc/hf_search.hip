@@ -542,8 +542,14 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   uint64_t* qsk;
   HF_TRY(ws.alloc(&qcodes, (size_t)(nq * d)));
   HF_TRY(ws.alloc(&qsk, (size_t)(nq * 8)));
-  HF_TRY(quantize(Q, f->dtype, nq * d, f->e, qcodes, s));
-  HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws));
+  {
+    StageTimer tm(ST_QCODES, s);
+    HF_TRY(quantize(Q, f->dtype, nq * d, f->e, qcodes, s));
+  }
+  {
+    StageTimer tm(ST_QSKETCH, s);
+    HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws));
+  }
   uint32_t* win = win_out;
   if (!win) HF_TRY(ws.alloc(&win, (size_t)(nq * T)));
   int64_t* doff;
@@ -551,6 +557,7 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   HIP_TRY(hipMemcpyAsync(doff, f->node_off.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
   {
     dim3 grid((unsigned)ceil_div(nq, 256), (unsigned)T);
+    StageTimer tm(ST_DESCEND, s);
     k_descend<<<grid, 256, 0, s>>>(f->nodes, doff, qcodes, nq, d, T, N, (int)p.k1, 8 * d + 2, win);
     HF_LAUNCH_CHECK();
   }
@@ -600,13 +607,22 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   };
   for (int64_t q0 = 0; q0 < nq; q0 += batch) {
     const int64_t nb = std::min(batch, nq - q0);
-    k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, f->sk_pos, qsk + q0 * 8,
-                                       ham, hist);
-    HF_LAUNCH_CHECK();
-    k_select<<<(unsigned)nb, SEL_T, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, ham, hist, k2,
-                                            pos_bits, c2 + q0 * k2, c2n + q0);
-    HF_LAUNCH_CHECK();
-    HF_TRY(rerank(q0, nb));
+    {
+      StageTimer tm(ST_HAM, s);
+      k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, f->sk_pos,
+                                         qsk + q0 * 8, ham, hist);
+      HF_LAUNCH_CHECK();
+    }
+    {
+      StageTimer tm(ST_SELECT, s);
+      k_select<<<(unsigned)nb, SEL_T, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, ham, hist, k2,
+                                              pos_bits, c2 + q0 * k2, c2n + q0);
+      HF_LAUNCH_CHECK();
+    }
+    {
+      StageTimer tm(ST_RERANK, s);
+      HF_TRY(rerank(q0, nb));
+    }
   }
   return HF_OK;
 }

@@ -219,6 +219,17 @@ def bench_graph(args, hf, torch, ws):
     log("drawing %d x %d data on the device" % (N, d))
     x = datagen.mixture_device(N, d, ws["n_comp"], ws["sigma"], ws["seed"], ws["unit"])
     torch.cuda.synchronize()
+    if args.sweep:
+        rows = torch.randperm(N, generator=torch.Generator(device="cpu").manual_seed(4))[:10000].to(x.device)
+        gt = ground_truth_graph(x, rows, args.k)
+        for cfg in args.sweep.split(";"):
+            no, wi = (int(v) for v in cfg.split(","))
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ids, _ = hf.knn_graph(x, no, wi, args.k, 3)
+            torch.cuda.synchronize()
+            log("graph sweep orders=%d w=%d: recall %.4f, %.3f s" % (no, wi, recall(ids[rows], gt),
+                                                                    time.perf_counter() - t))
     for _ in range(args.warmup):
         hf.knn_graph(x, args.orders, args.window, args.k, 3)
     torch.cuda.synchronize()
@@ -269,7 +280,20 @@ def main():
     ap.add_argument("--window", type=int, default=32)
     ap.add_argument("--sweep", default=None, help="extra search configs 'k1,k2,h;k1,k2,h'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration for rocprofv3)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: multi-GPU runs are not part of this build (got --gpus %d)"
               % args.gpus, file=sys.stderr)

@@ -260,7 +260,12 @@ hf_status hf_hilbert_sort(const uint8_t* codes_dev, int64_t N, int32_t d, uint64
   HF_TRY(ws.alloc(&drefl, d));
   HIP_TRY(hipMemcpyAsync(dperm, perm.data() + (size_t)tree * d, 4 * d, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(drefl, refl.data() + (size_t)tree * d, d, hipMemcpyHostToDevice, s));
-  HF_TRY(hilbert_sort_dev(codes_dev, N, d, dperm, drefl, order_dev, split_dev, ws));
+  uint32_t* msb = nullptr;
+  if (msb_words(d) > 0) {
+    HF_TRY(ws.alloc(&msb, (size_t)(N * msb_words(d))));
+    HF_TRY(msb_plane(codes_dev, N, d, msb, s));
+  }
+  HF_TRY(hilbert_sort_dev(codes_dev, msb, N, d, dperm, drefl, order_dev, split_dev, ws));
   HIP_TRY(hipStreamSynchronize(s));
   return HF_OK;
 }
@@ -333,6 +338,11 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   HIP_TRY(hipMemcpyAsync(f->curve_refl, refl.data(), (size_t)T * d, hipMemcpyHostToDevice, s));
   uint32_t* pos;
   HF_TRY(ws.alloc(&pos, N));
+  uint32_t* msb = nullptr;
+  if (msb_words(d) > 0) {
+    HF_TRY(ws.alloc(&msb, (size_t)(N * msb_words(d))));
+    HF_TRY(msb_plane(codes, N, d, msb, s));
+  }
   std::vector<uint32_t*> tnodes(T, nullptr);
   std::vector<int64_t> tcount(T, 0);
   struct NodeGuard {
@@ -356,7 +366,7 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
     const uint8_t* rt = f->curve_refl + (size_t)t * d;
     {
       StageTimer tm(ST_BSORT, s);
-      HF_TRY(hilbert_sort_dev(codes, N, d, pt, rt, order, split, wt));
+      HF_TRY(hilbert_sort_dev(codes, msb, N, d, pt, rt, order, split, wt));
     }
     {
       StageTimer tm(ST_BTRIE, s);

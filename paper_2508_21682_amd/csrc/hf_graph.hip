@@ -40,118 +40,169 @@ __global__ void k_init_lists(int32_t* __restrict__ ids, float* __restrict__ sc, 
   }
 }
 
+// Rows (and their norms) re-laid in the order's sequence so the band tiles
+// read contiguous memory.
+__global__ void k_gather_sorted(const __half* __restrict__ X, const float* __restrict__ nrm,
+                                const uint32_t* __restrict__ order, int64_t N, int d,
+                                __half* __restrict__ Xs, float* __restrict__ ns) {
+  const int64_t nv = d / 8;  // 16-byte vectors per row
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N * nv; i += (int64_t)gridDim.x * 256) {
+    const int64_t r = i / nv, c = i - r * nv;
+    const uint32_t id = order[r];
+    ((uint4*)Xs)[r * nv + c] = ((const uint4*)(X + (int64_t)id * d))[c];
+    if (c == 0) ns[r] = nrm[id];
+  }
+}
+
 __device__ __forceinline__ bool better(float s1, int32_t c1, float s2, int32_t c2) {
   return s1 > s2 || (s1 == s2 && (uint32_t)c1 < (uint32_t)c2);
 }
 
+// Top-k list of one row in registers, best first; (ws, wi) caches the k-th
+// entry so a rejected candidate costs one comparison.
 template <int KMAX>
-__device__ __forceinline__ void list_insert(float (&ls)[KMAX], int32_t (&li)[KMAX], int k, float s,
-                                            int32_t c) {
-  // reject if not better than the current k-th
-  float ws = -INFINITY;
-  int32_t wi = -1;
+struct TopList {
+  float ls[KMAX];
+  int32_t li[KMAX];
+  float ws;
+  int32_t wi;
+  __device__ __forceinline__ void refresh(int k) {
 #pragma unroll
-  for (int i = 0; i < KMAX; ++i)
-    if (i == k - 1) {
-      ws = ls[i];
-      wi = li[i];
-    }
-  if (!(wi < 0 || better(s, c, ws, wi))) return;
-  bool dup = false;
+    for (int i = 0; i < KMAX; ++i)
+      if (i == k - 1) {
+        ws = ls[i];
+        wi = li[i];
+      }
+  }
+  __device__ __forceinline__ void insert(int k, float s, int32_t c) {
+    if (!(wi < 0 || better(s, c, ws, wi))) return;
+    bool dup = false;
 #pragma unroll
-  for (int i = 0; i < KMAX; ++i) dup |= (i < k) && (li[i] == c);
-  if (dup) return;
-  // shift worse entries down by one, place the candidate
-  bool placed = false;
+    for (int i = 0; i < KMAX; ++i) dup |= (i < k) && (li[i] == c);
+    if (dup) return;
+    bool placed = false;
 #pragma unroll
-  for (int i = KMAX - 1; i >= 1; --i) {
-    if (i < k && !placed) {
-      if (li[i - 1] < 0 || better(s, c, ls[i - 1], li[i - 1])) {
-        ls[i] = ls[i - 1];
-        li[i] = li[i - 1];
-      } else {
-        ls[i] = s;
-        li[i] = c;
-        placed = true;
+    for (int i = KMAX - 1; i >= 1; --i) {
+      if (i < k && !placed) {
+        if (li[i - 1] < 0 || better(s, c, ls[i - 1], li[i - 1])) {
+          ls[i] = ls[i - 1];
+          li[i] = li[i - 1];
+        } else {
+          ls[i] = s;
+          li[i] = c;
+          placed = true;
+        }
       }
     }
+    if (!placed) {
+      ls[0] = s;
+      li[0] = c;
+    }
+    refresh(k);
   }
-  if (!placed) {
-    ls[0] = s;
-    li[0] = c;
-  }
-}
+};
 
-__device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t id, int d, int k0) {
-  if (id < 0 || k0 >= d) return (half8)(0);
-  uint4 raw = *(const uint4*)(X + id * d + k0);
+__device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t r, int d, int k0) {
+  if (r < 0 || k0 >= d) return (half8)(0);
+  uint4 raw = *(const uint4*)(X + r * d + k0);
   return __builtin_bit_cast(half8, raw);
 }
 
+// LDS written and read by the same wavefront only: order the accesses
+// without a block barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int KMAX, int KS>
-__global__ __launch_bounds__(256) void k_band(const __half* __restrict__ X, int64_t N, int d,
+__global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int64_t N, int d,
                                               const uint32_t* __restrict__ order,
-                                              const float* __restrict__ nrm, int w, int k,
+                                              const float* __restrict__ ns, int w, int k,
                                               int32_t* __restrict__ gids, float* __restrict__ gsc) {
   __shared__ float band[4][16][17];
+  __shared__ int32_t colid[4][16];
+  __shared__ float coln[4][16];
   const int wv = threadIdx.x / 64, l = __lane_id();
-  // every wave runs the whole loop (the block barriers below need all four)
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
+  if (r0 >= N) return;  // no block barriers below: waves are independent
   const int ri = l % 16, kg = l / 16;
-  const int64_t arow = r0 + ri < N ? (int64_t)order[r0 + ri] : -1;
+  const int64_t arow = r0 + ri < N ? r0 + ri : -1;
   half8 A[KS];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) A[s] = load_row8(X, arow, d, 32 * s + 8 * kg);
+  for (int s = 0; s < KS; ++s) A[s] = load_row8(Xs, arow, d, 32 * s + 8 * kg);
   // the owner lane (l < 16) holds the list of row r0 + l
-  float ls[KMAX];
-  int32_t li[KMAX];
+  TopList<KMAX> L;
   const int64_t own = r0 + l;
   const bool owner = l < 16 && own < N;
   const int64_t own_id = owner ? (int64_t)order[own] : 0;
-  const float own_n = owner ? nrm[own_id] : 1.f;
+  const float own_n = owner ? ns[own] : 1.f;
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
-    ls[i] = -INFINITY;
-    li[i] = -1;
+    L.ls[i] = -INFINITY;
+    L.li[i] = -1;
     if (owner && i < k) {
-      ls[i] = gsc[own_id * k + i];
-      li[i] = gids[own_id * k + i];
+      L.ls[i] = gsc[own_id * k + i];
+      L.li[i] = gids[own_id * k + i];
     }
   }
+  L.refresh(k);
   const int wr = (w + 15) / 16;
   const int nblk = 1 + 2 * wr;
+  half8 B[KS];
+  int32_t cid;
+  float cn;
+  {
+    const int64_t cpos = r0 - 16 * (int64_t)wr + ri;
+    const int64_t brow = (cpos >= 0 && cpos < N) ? cpos : -1;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) B[s] = load_row8(Xs, brow, d, 32 * s + 8 * kg);
+    cid = brow >= 0 ? (int32_t)order[brow] : -1;
+    cn = brow >= 0 ? ns[brow] : 1.f;
+  }
   for (int cb = 0; cb < nblk; ++cb) {
     const int64_t c0 = r0 + 16 * (int64_t)(cb - wr);
-    const int64_t cpos = c0 + ri;
-    const int64_t brow = (cpos >= 0 && cpos < N) ? (int64_t)order[cpos] : -1;
     float4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      half8 B = load_row8(X, brow, d, 32 * s + 8 * kg);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B, acc, 0, 0, 0);
-    }
+    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B[s], acc, 0, 0, 0);
     // D layout: lane l holds rows 4*(l/16)+r, column l%16
 #pragma unroll
     for (int r = 0; r < 4; ++r) band[wv][4 * kg + r][ri] = acc[r];
-    __syncthreads();
+    if (kg == 0) {
+      colid[wv][ri] = cid;
+      coln[wv][ri] = cn;
+    }
+    // prefetch the next column block while this one is merged
+    if (cb + 1 < nblk) {
+      const int64_t cpos = c0 + 16 + ri;
+      const int64_t brow = (cpos >= 0 && cpos < N) ? cpos : -1;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) B[s] = load_row8(Xs, brow, d, 32 * s + 8 * kg);
+      cid = brow >= 0 ? (int32_t)order[brow] : -1;
+      cn = brow >= 0 ? ns[brow] : 1.f;
+    }
+    wave_lds_sync();
     if (owner) {
+#pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int64_t cp = c0 + j;
         const int64_t delta = cp - own;
         if (delta == 0 || delta > w || -delta > w || cp < 0 || cp >= N) continue;
-        const int32_t cid = (int32_t)order[cp];
-        const float cs = band[wv][l][j] / (own_n * nrm[cid]);
-        list_insert<KMAX>(ls, li, k, cs, cid);
+        const float cs = band[wv][l][j] / (own_n * coln[wv][j]);
+        const int32_t c = colid[wv][j];
+        if (!(L.wi < 0 || better(cs, c, L.ws, L.wi))) continue;
+        L.insert(k, cs, c);
       }
     }
-    __syncthreads();
+    wave_lds_sync();
   }
   if (owner) {
 #pragma unroll
     for (int i = 0; i < KMAX; ++i)
       if (i < k) {
-        gsc[own_id * k + i] = ls[i];
-        gids[own_id * k + i] = li[i];
+        gsc[own_id * k + i] = L.ls[i];
+        gids[own_id * k + i] = L.li[i];
       }
   }
 }
@@ -198,10 +249,19 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   uint8_t* codes;
   float* nrm;
   uint32_t* order;
+  __half* Xs;
+  float* ns;
+  HF_TRY(ws.alloc(&Xs, (size_t)(N * d)));
+  HF_TRY(ws.alloc(&ns, (size_t)N));
   HF_TRY(ws.alloc(&codes, (size_t)(N * d)));
   HF_TRY(ws.alloc(&nrm, (size_t)N));
   HF_TRY(ws.alloc(&order, (size_t)N));
   HF_TRY(quantize(X, HF_F16, N * d, e, codes, s));
+  uint32_t* msb = nullptr;
+  if (msb_words(d) > 0) {
+    HF_TRY(ws.alloc(&msb, (size_t)(N * msb_words(d))));
+    HF_TRY(msb_plane(codes, N, d, msb, s));
+  }
   k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, nrm);
   k_init_lists<<<grid_for(N * p.k), 256, 0, s>>>(ids, scores, N * p.k);
   HF_LAUNCH_CHECK();
@@ -219,13 +279,15 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     Workspace wt(s);
     {
       StageTimer tm(ST_GSORT, s);
-      HF_TRY(hilbert_sort_dev(codes, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
+      HF_TRY(hilbert_sort_dev(codes, msb, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
     }
     StageTimer tm(ST_GBAND, s);
+    k_gather_sorted<<<grid_for(N * (d / 8)), 256, 0, s>>>(X, nrm, order, N, d, Xs, ns);
+    HF_LAUNCH_CHECK();
     if (p.k <= 16)
-      HF_TRY(launch_band<16>(ks, X, N, d, order, nrm, (int)p.window, (int)p.k, ids, scores, s));
+      HF_TRY(launch_band<16>(ks, Xs, N, d, order, ns, (int)p.window, (int)p.k, ids, scores, s));
     else
-      HF_TRY(launch_band<32>(ks, X, N, d, order, nrm, (int)p.window, (int)p.k, ids, scores, s));
+      HF_TRY(launch_band<32>(ks, Xs, N, d, order, ns, (int)p.window, (int)p.k, ids, scores, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   return HF_OK;

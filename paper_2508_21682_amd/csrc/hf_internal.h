@@ -174,15 +174,20 @@ hf_status minmax(const void* X, hf_dtype dt, int64_t n, float* mn_host, float* m
 int choose_exp(float mn, float mx);
 hf_status quantize(const void* X, hf_dtype dt, int64_t n, int e, uint8_t* out, hipStream_t s);
 // hf_keys.hip
-hf_status key_chunks(const uint8_t* codes, int d, const int32_t* perm, const uint8_t* refl,
-                     const uint32_t* items, int64_t n_items, int chunk, uint64_t* out,
-                     hipStream_t s);
+// msb: optional top-bit plane (msb_words(d) words per point) for top-level chunks.
+int msb_words(int d);
+hf_status msb_plane(const uint8_t* codes, int64_t N, int d, uint32_t* msb, hipStream_t s);
+hf_status key_chunks(const uint8_t* codes, const uint32_t* msb, int d, const int32_t* perm,
+                     const uint8_t* refl, const uint32_t* items, int64_t n_items, int chunk,
+                     uint64_t* out, hipStream_t s);
 hf_status node_tests(const uint8_t* codes, int d, const int32_t* perm, const uint8_t* refl,
                      const uint32_t* points, const uint32_t* bits, int64_t n, uint32_t* out_w1,
                      hipStream_t s);
 // hf_sort.hip: Hilbert sort with a curve already on the device.
-hf_status hilbert_sort_dev(const uint8_t* codes, int64_t N, int d, const int32_t* perm,
-                           const uint8_t* refl, uint32_t* order, uint32_t* split, Workspace& ws);
+// msb (nullable): top-bit plane of the codes, computed once per code set.
+hf_status hilbert_sort_dev(const uint8_t* codes, const uint32_t* msb, int64_t N, int d,
+                           const int32_t* perm, const uint8_t* refl, uint32_t* order, uint32_t* split,
+                           Workspace& ws);
 // hf_trie.hip: pre-order trie records (2 words each) from a sorted order and its split bits.
 hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_t* perm,
                      const uint8_t* refl, const uint32_t* order, const uint32_t* split,

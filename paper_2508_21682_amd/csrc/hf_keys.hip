@@ -213,6 +213,55 @@ __global__ __launch_bounds__(256) void node_test_kernel(const uint8_t* __restric
   }
 }
 
+// Top bit of every code, 32 axes per word (bit i%32 of word i/32).
+__global__ void k_msb_plane(const uint8_t* __restrict__ codes, int64_t N, int d, int nw,
+                            uint32_t* __restrict__ msb) {
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < N * nw;
+       idx += (int64_t)gridDim.x * 256) {
+    const int64_t p = idx / nw;
+    const int w = (int)(idx - p * nw);
+    const uint8_t* row = codes + p * d;
+    uint32_t v = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int i = 32 * w + b;
+      if (i < d) v |= (uint32_t)(row[i] >> 7) << b;
+    }
+    msb[idx] = v;
+  }
+}
+
+// Chunks that lie inside the top level need no undo sweep: key bit j is the
+// parity of the (reflected) top bits of tree axes 0..j.  One thread per point,
+// the point's top bits in registers, tree axes read as uniform indices.
+template <int NW>
+__global__ __launch_bounds__(256) void chunk_top_kernel(const uint32_t* __restrict__ msb,
+                                                        const int32_t* __restrict__ perm,
+                                                        const uint8_t* __restrict__ refl,
+                                                        const uint32_t* __restrict__ items,
+                                                        int64_t n, int chunk,
+                                                        uint64_t* __restrict__ out) {
+  const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (it >= n) return;
+  const uint32_t p = items ? items[it] : (uint32_t)it;
+  uint32_t m[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) m[w] = msb[(int64_t)p * NW + w];
+  uint32_t run = 0;
+  uint64_t key = 0;
+  const int i0 = 64 * chunk;
+  for (int i = 0; i < i0; ++i) {
+    const int a = perm[i];
+    run ^= ((m[a >> 5] >> (a & 31)) & 1u) ^ (uint32_t)refl[i];
+  }
+#pragma unroll 8
+  for (int j = 0; j < 64; ++j) {
+    const int a = perm[i0 + j];
+    run ^= ((m[a >> 5] >> (a & 31)) & 1u) ^ (uint32_t)refl[i0 + j];
+    key |= (uint64_t)run << (63 - j);
+  }
+  out[it] = key;
+}
+
 int pick_g(int d) {
   int g = (d + 63) / 64;
   int G = 1;
@@ -233,10 +282,36 @@ int pick_g(int d) {
     default: KERNEL<64><<<grid, 256, 0, s>>>(__VA_ARGS__); break;                    \
   }
 
-hf_status key_chunks(const uint8_t* codes, int d, const int32_t* perm, const uint8_t* refl,
-                     const uint32_t* items, int64_t n_items, int chunk, uint64_t* out,
-                     hipStream_t s) {
+int msb_words(int d) {
+  const int nw = (d + 31) / 32;
+  return nw <= 1 ? 1 : nw <= 2 ? 2 : nw <= 4 ? 4 : nw <= 8 ? 8 : nw <= 12 ? 12 : nw <= 16 ? 16 : 0;
+}
+
+hf_status msb_plane(const uint8_t* codes, int64_t N, int d, uint32_t* msb, hipStream_t s) {
+  const int nw = msb_words(d);
+  if (nw == 0 || N <= 0) return HF_OK;
+  k_msb_plane<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, ceil_div(N * nw, 256))), 256, 0, s>>>(
+      codes, N, d, nw, msb);
+  HF_LAUNCH_CHECK();
+  return HF_OK;
+}
+
+hf_status key_chunks(const uint8_t* codes, const uint32_t* msb, int d, const int32_t* perm,
+                     const uint8_t* refl, const uint32_t* items, int64_t n_items, int chunk,
+                     uint64_t* out, hipStream_t s) {
   if (n_items <= 0) return HF_OK;
+  const int nw = msb_words(d);
+  if (msb && nw > 0 && (int64_t)chunk * 64 + 64 <= d) {
+    dim3 grid((unsigned)ceil_div(n_items, 256));
+    switch (nw) {
+#define HF_NW(n) \
+  case n: chunk_top_kernel<n><<<grid, 256, 0, s>>>(msb, perm, refl, items, n_items, chunk, out); break;
+      HF_NW(1) HF_NW(2) HF_NW(4) HF_NW(8) HF_NW(12) HF_NW(16)
+#undef HF_NW
+    }
+    HF_LAUNCH_CHECK();
+    return HF_OK;
+  }
   dim3 grid((unsigned)ceil_div(n_items, 4));
   int G = pick_g(d);
   HF_DISPATCH_G(G, chunk_kernel, codes, d, perm, refl, items, n_items, chunk, out);

@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256) void k_descend(const uint32_t* __restrict__ no
 constexpr int HB = 513;  // Hamming values 0..512
 
 __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_perm, int64_t N,
-                                             int T, int len, const uint32_t* __restrict__ win,
+                                             int T, int len, int64_t qstride,
+                                             const uint32_t* __restrict__ win,
                                              const uint64_t* __restrict__ sk,
                                              const uint64_t* __restrict__ qsk,
                                              uint16_t* __restrict__ ham,
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
   __syncthreads();
   const int w = threadIdx.x / 64, grp = threadIdx.x / 4, qd = threadIdx.x & 3;
   const uint64_t q0 = qsk[q * 8 + 2 * qd], q1 = qsk[q * 8 + 2 * qd + 1];
-  uint16_t* out = ham + q * (int64_t)T * len;
+  uint16_t* out = ham + q * qstride;
   for (int t = 0; t < T; ++t) {
     const uint32_t* P = tree_perm + (int64_t)t * N + win[q * T + t];
     uint16_t* o = out + (int64_t)t * len;
@@ -140,8 +141,41 @@ __device__ __forceinline__ void bitonic_u64(uint64_t* a, int n2) {
     }
 }
 
+// Visits every window entry of one query: the Hamming values are read 8 at a
+// time (16-byte loads of the query's padded row), the tree position of an
+// entry is read only when `want(ham)` holds.  f(ham, pos) runs per wanted entry.
+template <class W, class F>
+__device__ __forceinline__ void scan_entries(const uint16_t* __restrict__ hq,
+                                             const uint32_t* __restrict__ tree_perm, int64_t N,
+                                             const uint32_t* __restrict__ wq, int len, int64_t total,
+                                             W want, F f) {
+  const int64_t n8 = (total + 7) / 8;
+  for (int64_t j0 = threadIdx.x; j0 < n8; j0 += 2 * SEL_T) {
+    uint4 v[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t j = j0 + (int64_t)u * SEL_T;
+      v[u] = j < n8 ? *(const uint4*)(hq + 8 * j) : make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t j = j0 + (int64_t)u * SEL_T;
+      const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int hv = (int)((w[s >> 1] >> (16 * (s & 1))) & 0xFFFFu);
+        const int64_t e = 8 * j + s;
+        if (e < total && want(hv)) {
+          const uint32_t t = (uint32_t)(e / len), i = (uint32_t)(e - (int64_t)t * len);
+          f(hv, tree_perm[(int64_t)t * N + wq[t] + i]);
+        }
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ tree_perm,
-                                                  int64_t N, int T, int len,
+                                                  int64_t N, int T, int len, int64_t qstride,
                                                   const uint32_t* __restrict__ win,
                                                   const uint16_t* __restrict__ ham,
                                                   const uint32_t* __restrict__ hist0, int k2,
@@ -156,7 +190,7 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
   __shared__ uint32_t s_plo, s_pend, s_phi;
 
   const int64_t q = blockIdx.x;
-  const uint16_t* hq = ham + q * (int64_t)T * len;
+  const uint16_t* hq = ham + q * qstride;
   const uint32_t* wq = win + q * T;
   const int HM = (int)((1ull << (32 - pos_bits)) - 1ull);
   const uint32_t pmask = (uint32_t)((1ull << pos_bits) - 1ull);
@@ -174,15 +208,12 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
     } else {
       for (int i = threadIdx.x; i < HB; i += SEL_T) hist[i] = 0;
       __syncthreads();
-      for (int t = 0; t < T; ++t) {
-        const uint32_t* P = tree_perm + (int64_t)t * N + wq[t];
-        for (int i = threadIdx.x; i < len; i += SEL_T) {
-          int hv = hq[(int64_t)t * len + i];
-          if (hv < lo_ham) continue;
-          if (hv == lo_ham && P[i] < lo_pos) continue;
-          atomicAdd(&hist[hv], 1u);
-        }
-      }
+      const int lh = lo_ham;
+      const uint32_t lp = lo_pos;
+      scan_entries(hq, tree_perm, N, wq, len, total, [&](int hv) { return hv >= lh; },
+                   [&](int hv, uint32_t p) {
+                     if (hv > lh || p >= lp) atomicAdd(&hist[hv], 1u);
+                   });
       __syncthreads();
     }
     first = false;
@@ -193,13 +224,17 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
           hf = h;
           break;
         }
+      // bins from hf on until they hold `need` entries plus a margin for
+      // duplicates (few: windows of different trees rarely overlap), or CAP
       int hb = -1;
       if (hf >= 0) {
         uint32_t cum = 0;
+        const uint32_t enough = (uint32_t)need + (uint32_t)need / 8u + 64u;
         for (int h = hf; h < HB && h - hf < HM; ++h) {
           if (cum + hist[h] > (uint32_t)CAP) break;
           cum += hist[h];
           hb = h;
+          if (cum >= enough) break;
         }
       }
       s_hf = hf;
@@ -220,15 +255,10 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
         const uint32_t width = (uint32_t)ceil_div((int64_t)(phi - plo), NBK);
         for (int i = threadIdx.x; i < NBK; i += SEL_T) bk[i] = 0;
         __syncthreads();
-        for (int t = 0; t < T; ++t) {
-          const uint32_t* P = tree_perm + (int64_t)t * N + wq[t];
-          for (int i = threadIdx.x; i < len; i += SEL_T) {
-            if (hq[(int64_t)t * len + i] != hf) continue;
-            uint32_t p = P[i];
-            if (p < plo || p >= phi) continue;
-            atomicAdd(&bk[(p - plo) / width], 1u);
-          }
-        }
+        scan_entries(hq, tree_perm, N, wq, len, total, [&](int hv) { return hv == hf; },
+                     [&](int, uint32_t p) {
+                       if (p >= plo && p < phi) atomicAdd(&bk[(p - plo) / width], 1u);
+                     });
         __syncthreads();
         if (threadIdx.x == 0) {
           uint32_t cum = 0;
@@ -251,25 +281,20 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
       }
     }
     // collect the chunk
-    const uint32_t plo = s_plo, pend = s_pend;
-    for (int t = 0; t < T; ++t) {
-      const uint32_t* P = tree_perm + (int64_t)t * N + wq[t];
-      for (int i = threadIdx.x; i < len; i += SEL_T) {
-        int hv = hq[(int64_t)t * len + i];
-        uint32_t p = P[i];
-        bool take;
-        uint32_t key;
-        if (mode == 1) {
-          take = hv >= hf && hv <= hb && !(hv == lo_ham && p < lo_pos);
-          key = ((uint32_t)(hv - hf) << pos_bits) | p;
-        } else {
-          take = hv == hf && p >= plo && p < pend;
-          key = p;
-        }
-        if (take) {
-          uint32_t slot = atomicAdd(&s_cnt, 1u);
-          keys[slot] = key;
-        }
+    {
+      const uint32_t plo = s_plo, pend = s_pend;
+      const int lh = lo_ham;
+      const uint32_t lp = lo_pos;
+      if (mode == 1) {
+        scan_entries(hq, tree_perm, N, wq, len, total, [&](int hv) { return hv >= hf && hv <= hb; },
+                     [&](int hv, uint32_t p) {
+                       if (hv > lh || p >= lp) keys[atomicAdd(&s_cnt, 1u)] = ((uint32_t)(hv - hf) << pos_bits) | p;
+                     });
+      } else {
+        scan_entries(hq, tree_perm, N, wq, len, total, [&](int hv) { return hv == hf; },
+                     [&](int, uint32_t p) {
+                       if (p >= plo && p < pend) keys[atomicAdd(&s_cnt, 1u)] = p;
+                     });
       }
     }
     __syncthreads();
@@ -304,10 +329,9 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
       if (lo_ham >= HB) break;
     } else {
       lo_ham = hf;
-      lo_pos = pend;
+      lo_pos = s_pend;
     }
     __syncthreads();
-    if (total == 0) break;
   }
   for (int i = outn + threadIdx.x; i < k2; i += SEL_T) c2[q * k2 + i] = NONE32;
   if (threadIdx.x == 0) c2n[q] = outn;
@@ -334,7 +358,10 @@ __device__ __forceinline__ uint32_t epos(const uint32_t* st, const uint32_t* off
   return st[lo] + (e - off[lo]);
 }
 
-template <class T, bool VEC>
+constexpr int RROWS = 4;
+
+// MCH > 0: rows read as 16-byte chunks, MCH chunks per lane; MCH == 0: scalar reads.
+template <class T, int MCH>
 __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64_t N, int d,
                                                  const T* __restrict__ Q,
                                                  const uint32_t* __restrict__ c2,
@@ -398,48 +425,80 @@ __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64
     __syncthreads();
   }
   const uint32_t E = s_E;
-  // scores: one row per 16-lane group
+  // scores: a 16-lane group per row, RROWS consecutive expansion rows in
+  // flight per group (mostly adjacent master positions: contiguous reads)
   {
     const int g = threadIdx.x / 16, gl = threadIdx.x % 16;
-    for (uint32_t e = g; e < E; e += RR_T / 16) {
-      uint32_t p = epos(st, off, n2, e);
-      const T* row = Xp + (int64_t)p * d;
-      float acc = 0.f;
-      if constexpr (VEC) {
-        constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
-        const int nch = d / EPC;
-        for (int c = gl; c < nch; c += 16) {
-          uint4 raw = *(const uint4*)(row + c * EPC);
-          const float* qq = sq + c * EPC;
-          if constexpr (sizeof(T) == 2) {
-            const __half2* hv = (const __half2*)&raw;
+    constexpr int NG = RR_T / 16;
+    constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
+    const int nch = d / EPC;
+    for (uint32_t e0 = (uint32_t)g * RROWS; e0 < E; e0 += NG * RROWS) {
+      float acc[RROWS];
+      if constexpr (MCH > 0) {
+        uint4 raw[RROWS][MCH];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              float2 f = __half22float2(hv[j]);
-              acc = fmaf(f.x, qq[2 * j], acc);
-              acc = fmaf(f.y, qq[2 * j + 1], acc);
-            }
-          } else {
-            const float* fv = (const float*)&raw;
+        for (int u = 0; u < RROWS; ++u) {
+          const uint32_t e = e0 + u;
+          const T* row = Xp + (int64_t)(e < E ? epos(st, off, n2, e) : 0u) * d;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc = fmaf(fv[j], qq[j], acc);
+          for (int m = 0; m < MCH; ++m) {
+            const int c = gl + 16 * m;
+            raw[u][m] = (e < E && c < nch) ? *(const uint4*)(row + c * EPC) : make_uint4(0, 0, 0, 0);
           }
         }
+#pragma unroll
+        for (int u = 0; u < RROWS; ++u) {
+          float a = 0.f;
+#pragma unroll
+          for (int m = 0; m < MCH; ++m) {
+            const int c = gl + 16 * m;
+            if (c < nch) {
+              const float* qq = sq + c * EPC;
+              if constexpr (sizeof(T) == 2) {
+                const __half2* hv = (const __half2*)&raw[u][m];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  float2 f2 = __half22float2(hv[j]);
+                  a = fmaf(f2.x, qq[2 * j], a);
+                  a = fmaf(f2.y, qq[2 * j + 1], a);
+                }
+              } else {
+                const float* fv = (const float*)&raw[u][m];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a = fmaf(fv[j], qq[j], a);
+              }
+            }
+          }
+          acc[u] = a;
+        }
       } else {
-        for (int c = gl; c < d; c += 16) {
-          float xv;
-          if constexpr (sizeof(T) == 2)
-            xv = __half2float(row[c]);
-          else
-            xv = row[c];
-          acc = fmaf(xv, sq[c], acc);
+#pragma unroll
+        for (int u = 0; u < RROWS; ++u) {
+          const uint32_t e = e0 + u;
+          float a = 0.f;
+          if (e < E) {
+            const T* row = Xp + (int64_t)epos(st, off, n2, e) * d;
+            for (int c = gl; c < d; c += 16) {
+              float xv;
+              if constexpr (sizeof(T) == 2)
+                xv = __half2float(row[c]);
+              else
+                xv = row[c];
+              a = fmaf(xv, sq[c], a);
+            }
+          }
+          acc[u] = a;
         }
       }
-      acc += __shfl_xor(acc, 8);
-      acc += __shfl_xor(acc, 4);
-      acc += __shfl_xor(acc, 2);
-      acc += __shfl_xor(acc, 1);
-      if (gl == 0) ekey[e] = ~float_to_ordered(acc);  // ascending key = descending score
+#pragma unroll
+      for (int u = 0; u < RROWS; ++u) {
+        float a = acc[u];
+        a += __shfl_xor(a, 8);
+        a += __shfl_xor(a, 4);
+        a += __shfl_xor(a, 2);
+        a += __shfl_xor(a, 1);
+        if (gl == 0 && e0 + u < E) ekey[e0 + u] = ~float_to_ordered(a);  // ascending key = descending score
+      }
     }
   }
   __syncthreads();
@@ -562,7 +621,7 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     HF_LAUNCH_CHECK();
   }
   // the second stage runs in batches of queries sized to bound scratch memory
-  const int64_t per_q = (int64_t)T * len;
+  const int64_t per_q = ((int64_t)T * len + 7) / 8 * 8;  // 16-byte aligned rows of distances
   int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1ll << 31) / (per_q * 2 + 1)));
   uint16_t* ham;
   uint32_t *hist, *c2 = c2_out;
@@ -582,40 +641,50 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     return HF_ERR_UNSUPPORTED;
   }
   const size_t esz = f->dtype == HF_F16 ? 2 : 4;
-  const bool vec = ((size_t)d * esz) % 16 == 0;
+  // chunks of 16 bytes per lane when rows are 16-byte multiples and short enough
+  int mch = 0;
+  if (((size_t)d * esz) % 16 == 0) {
+    const int per_lane = (int)ceil_div((int64_t)d * esz / 16, 16);
+    mch = per_lane <= 1 ? 1 : per_lane <= 2 ? 2 : per_lane <= 3 ? 3 : per_lane <= 4 ? 4 : per_lane <= 6 ? 6 : per_lane <= 8 ? 8 : 0;
+  }
   auto rerank = [&](int64_t q0, int64_t nb) -> hf_status {
     const void* Qb = (const char*)Q + q0 * d * esz;
+    const void* kern = nullptr;
+#define HF_RR(TY, M) if (mch == M) kern = (const void*)k_rerank<TY, M>;
     if (f->dtype == HF_F16) {
-      auto kern = vec ? k_rerank<__half, true> : k_rerank<__half, false>;
-      if (smem > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-      kern<<<(unsigned)nb, RR_T, smem, s>>>((const __half*)f->X_pos, N, d, (const __half*)Qb,
-                                            c2 + q0 * k2, c2n + q0, k2, (int)p.h, (int)p.k, k2p,
-                                            (int)emax, kp, f->pos2id, ids + q0 * p.k,
-                                            scores + q0 * p.k, en_out ? en_out + q0 : nullptr);
+      HF_RR(__half, 0) HF_RR(__half, 1) HF_RR(__half, 2) HF_RR(__half, 3) HF_RR(__half, 4) HF_RR(__half, 6) HF_RR(__half, 8)
     } else {
-      auto kern = vec ? k_rerank<float, true> : k_rerank<float, false>;
-      if (smem > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-      kern<<<(unsigned)nb, RR_T, smem, s>>>((const float*)f->X_pos, N, d, (const float*)Qb,
-                                            c2 + q0 * k2, c2n + q0, k2, (int)p.h, (int)p.k, k2p,
-                                            (int)emax, kp, f->pos2id, ids + q0 * p.k,
-                                            scores + q0 * p.k, en_out ? en_out + q0 : nullptr);
+      HF_RR(float, 0) HF_RR(float, 1) HF_RR(float, 2) HF_RR(float, 3) HF_RR(float, 4) HF_RR(float, 6) HF_RR(float, 8)
     }
-    HF_LAUNCH_CHECK();
+#undef HF_RR
+    if (smem > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    const void* Xp = f->X_pos;
+    const uint32_t* c2b = c2 + q0 * k2;
+    const int32_t* c2nb = c2n + q0;
+    int h_ = (int)p.h, k_ = (int)p.k, emax_ = (int)emax;
+    const uint32_t* p2i = f->pos2id;
+    int32_t* idsb = ids + q0 * p.k;
+    float* scb = scores + q0 * p.k;
+    int32_t* enb = en_out ? en_out + q0 : nullptr;
+    int64_t N_ = N;
+    int d_ = d, k2_ = k2, k2p_ = k2p, kp_ = kp;
+    void* args[] = {(void*)&Xp, &N_, &d_, (void*)&Qb, (void*)&c2b, (void*)&c2nb, &k2_, &h_, &k_, &k2p_,
+                    &emax_, &kp_, (void*)&p2i, (void*)&idsb, (void*)&scb, (void*)&enb};
+    HIP_TRY(hipLaunchKernel(kern, dim3((unsigned)nb), dim3(RR_T), args, smem, s));
     return HF_OK;
   };
   for (int64_t q0 = 0; q0 < nq; q0 += batch) {
     const int64_t nb = std::min(batch, nq - q0);
     {
       StageTimer tm(ST_HAM, s);
-      k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, f->sk_pos,
+      k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, per_q, win + q0 * T, f->sk_pos,
                                          qsk + q0 * 8, ham, hist);
       HF_LAUNCH_CHECK();
     }
     {
       StageTimer tm(ST_SELECT, s);
-      k_select<<<(unsigned)nb, SEL_T, 0, s>>>(f->tree_perm, N, T, len, win + q0 * T, ham, hist, k2,
+      k_select<<<(unsigned)nb, SEL_T, 0, s>>>(f->tree_perm, N, T, len, per_q, win + q0 * T, ham, hist, k2,
                                               pos_bits, c2 + q0 * k2, c2n + q0);
       HF_LAUNCH_CHECK();
     }

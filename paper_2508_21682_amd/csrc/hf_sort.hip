@@ -125,8 +125,9 @@ inline unsigned grid_for(int64_t n) {
 
 }  // namespace
 
-hf_status hilbert_sort_dev(const uint8_t* codes, int64_t N, int d, const int32_t* perm,
-                           const uint8_t* refl, uint32_t* order, uint32_t* split, Workspace& ws) {
+hf_status hilbert_sort_dev(const uint8_t* codes, const uint32_t* msb, int64_t N, int d,
+                           const int32_t* perm, const uint8_t* refl, uint32_t* order, uint32_t* split,
+                           Workspace& ws) {
   hipStream_t s = ws.stream;
   const int W = (int)ceil_div((int64_t)d * 8, 64);
   uint32_t *A, *A2, *seg, *seg2, *pts, *npts, *nseg, *vals, *avals, *tied, *head, *excl, *srank,
@@ -167,7 +168,7 @@ hf_status hilbert_sort_dev(const uint8_t* codes, int64_t N, int d, const int32_t
   for (int c = 0; c < W && na > 1; ++c) {
     k_gather_pts<<<grid_for(na), 256, 0, s>>>(A, order, na, pts);
     HF_LAUNCH_CHECK();
-    HF_TRY(key_chunks(codes, d, perm, refl, pts, na, c, kc, s));
+    HF_TRY(key_chunks(codes, msb, d, perm, refl, pts, na, c, kc, s));
     k_init_kv<<<grid_for(na), 256, 0, s>>>(kc, na, keys, vals);
     HF_LAUNCH_CHECK();
     uint64_t *k1 = keys, *k2 = akeys;

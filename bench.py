@@ -78,6 +78,14 @@ def ground_truth_graph(x, rows, k, xchunk=1 << 20):
     return best_i
 
 
+def audit(hf, torch, x, q, ids, scores):
+    """Error of GPU scores against the FP64 audit kernel, over valid ids."""
+    exact = hf.audit_scores(x, q, ids.int().contiguous())
+    ok = ids >= 0
+    err = (scores.double() - exact).abs()[ok]
+    return {"max_abs": err.max().item(), "mean_abs": err.mean().item(), "pairs": int(ok.sum().item())}
+
+
 def recall(found, truth):
     import torch
 
@@ -207,6 +215,37 @@ def bench_search(args, hf, torch, ws):
            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
     if sweep:
         res["sweep"] = sweep
+    res["audit_fp32"] = audit(hf, torch, x, q, ids, sc)
+    if args.forms:
+        res["forms"] = {}
+        for prec in args.forms.split(","):
+            forest.add_precision(prec)
+            for _ in range(args.warmup):
+                forest.search(q, args.k, args.k1, args.k2, args.h, precision=prec)
+            hf.timing_enable(True)
+            hf.timing_read()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                pid, psc = forest.search(q, args.k, args.k1, args.k2, args.h, precision=prec)
+            torch.cuda.synchronize()
+            pdt = time.perf_counter() - t
+            pst = hf.timing_read()
+            hf.timing_enable(False)
+            sub = q[:1000]
+            r = forest.search_lowprec_debug(sub, args.k, args.k1, args.k2, args.h, prec)
+            p2i = forest.pos2id().long()
+            sp = r["surv_pos"].long()
+            ok = sp >= 0
+            sid = torch.where(ok, p2i[sp.clamp(min=0)], torch.full_like(sp, -1)).int()
+            lp_err = audit(hf, torch, x, sub, sid, r["surv_score"])
+            form = {"qps": nq * args.steps / pdt, "recall": recall(pid, gt), "ms_per_step": pdt * 1e3 / args.steps,
+                    "survivors": 4 * args.k, "audit_final_fp32": audit(hf, torch, x, q, pid, psc),
+                    "audit_lowprec_scores": lp_err,
+                    "stages_ms_per_step": {k_: v[0] / args.steps for k_, v in pst.items()}}
+            res["forms"][prec] = form
+            log("form %s: recall %.4f, %.0f QPS, low-precision score error max %.3g" % (
+                prec, form["recall"], form["qps"], lp_err["max_abs"]))
     forest.free()
     return res
 
@@ -279,6 +318,7 @@ def main():
     ap.add_argument("--orders", type=int, default=32)
     ap.add_argument("--window", type=int, default=32)
     ap.add_argument("--sweep", default=None, help="extra search configs 'k1,k2,h;k1,k2,h'")
+    ap.add_argument("--forms", default="bf16,fp8", help="precision forms measured after the plain search")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration for rocprofv3)")

@@ -210,6 +210,29 @@ hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype,
                           uint32_t* win_dev, uint32_t* c2_dev, int32_t* c2n_dev, int32_t* en_dev,
                           void* stream);
 
+/* Precision form (not in the paper): adds a BF16 copy (RNE of the stored
+ * rows) or an FP8 copy (OCP e4m3, per-row scale s = max|x|/448 in FP32, codes
+ * of x/s rounded to nearest even and saturated) of the master-ordered rows to
+ * the forest, so hf_search can score the expansion set E with
+ * params->precision = HF_PREC_BF16 / HF_PREC_FP8 on MFMA (FP32 accumulate),
+ * keep the best `survivors` (default 4k; ties by position) and rerank those in
+ * FP32 from the stored rows.  Adds 2 (BF16) or 1 + 4/d (FP8) bytes per
+ * element to the forest.  Synchronises. */
+hf_status hf_forest_add_precision(hf_forest* f, hf_precision prec, void* stream);
+
+/* hf_search in a low precision, also returning the survivors: surv_pos_dev
+ * nq x S master positions in (low-precision score desc, position) order,
+ * 0xFFFFFFFF past |E|; surv_score_dev nq x S their low-precision scores. */
+hf_status hf_search_lowprec_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64_t nq,
+                                  const hf_search_params* params, int32_t* ids_dev, float* scores_dev,
+                                  uint32_t* surv_pos_dev, float* surv_score_dev, void* stream);
+
+/* Error audit: FP64 inner products of query q with data row ids_dev[q*k + i]
+ * (original order X_dev, N x d), written to out_dev (nq x k doubles; 0 for
+ * id -1).  The only FP64 arithmetic on the GPU. */
+hf_status hf_audit_scores(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const void* Q_dev,
+                          int64_t nq, const int32_t* ids_dev, int32_t k, double* out_dev, void* stream);
+
 /* ------------------------------------------------------------------ timing */
 
 /* Per-kernel timing with hipEvents recorded on the caller's stream around

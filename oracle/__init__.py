@@ -61,6 +61,12 @@ def lib():
             "hfo_search_stage2": (None, [P, i32, i64, i32, P, P, i32, P, P, P, P, i64,
                                          i32, i32, i32, i32, P, P, P, P, P, P]),
             "hfo_graph_rows": (None, [P, i32, i64, i32, P, i32, i32, P, i64, i32, i32, P, P, P, P]),
+            "hfo_bf16": (C.c_double, [C.c_double]),
+            "hfo_e4m3_decode": (C.c_double, [C.c_uint8]),
+            "hfo_e4m3_encode": (C.c_uint8, [C.c_float]),
+            "hfo_fp8_scale": (C.c_float, [P, i32, i64, i32]),
+            "hfo_search_lowprec": (None, [P, i32, i64, i32, P, P, P, i32, P, i64, i32, i32, i32, i32,
+                                          P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -236,6 +242,35 @@ def search(F, q: np.ndarray, k1: int, k2: int, h: int, k: int):
                             _p(scores), _p(c2), _p(c2n), _p(c1n), _p(en))
     return dict(ids=ids, scores=scores, winstart=win, c2=c2, c2n=c2n, c1n=c1n, en=en, qcodes=qcodes,
                 qsk=qsk)
+
+
+def search_lowprec(F, q: np.ndarray, c2: np.ndarray, c2n: np.ndarray, h: int, k: int, prec: str, S: int):
+    """Precision form of the final selection from given C2 lists (emulated BF16/FP8)."""
+    code = {"bf16": 1, "fp8": 2}[prec]
+    x = np.ascontiguousarray(F["x"])
+    qq = np.ascontiguousarray(q.astype(x.dtype))
+    nq = q.shape[0]
+    k2 = c2.shape[1]
+    ids = np.empty((nq, k), np.int32)
+    sc = np.empty((nq, k), np.float64)
+    sp = np.empty((nq, S), np.uint32)
+    ss = np.empty((nq, S), np.float64)
+    lib().hfo_search_lowprec(_p(x), _dtype_code(x), F["N"], F["d"], _p(F["pos2id"]),
+                             _p(np.ascontiguousarray(c2, np.uint32)), _p(np.ascontiguousarray(c2n, np.int32)),
+                             k2, _p(qq), nq, h, k, code, S, _p(ids), _p(sc), _p(sp), _p(ss))
+    return dict(ids=ids, scores=sc, surv_pos=sp, surv_score=ss)
+
+
+def bf16(x: float) -> float:
+    return float(lib().hfo_bf16(x))
+
+
+def e4m3_decode(c: int) -> float:
+    return float(lib().hfo_e4m3_decode(c))
+
+
+def e4m3_encode(y: float) -> int:
+    return int(lib().hfo_e4m3_encode(y))
 
 
 # --------------------------------------------------------------------------- Alg. 2

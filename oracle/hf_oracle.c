@@ -507,6 +507,125 @@ void hfo_search_stage2(const void *X, int32_t dtype, int64_t N, int32_t d, const
 }
 
 /* ------------------------------------------------------------------------ */
+/* Precision form emulation (not in the paper).                              */
+/*  bf16: x rounded to 8 significant bits, nearest, ties to even.            */
+/*  fp8 (OCP e4m3): value of code c = sign * (m/8) * 2^-6 for exponent field */
+/*  0, (1 + m/8) * 2^(E-7) otherwise; 0x7F is NaN and never produced.  A      */
+/*  value is encoded as the finite code nearest to it (ties: even code),     */
+/*  saturating at 448.  Per-vector scale s = max|x| / 448 in binary32 (1 for */
+/*  a zero vector), codes of x / s computed in binary32.                     */
+/* Pinned: every code round-trips, encoding of midpoints goes to even codes, */
+/* the largest value is 448 and the smallest subnormal 2^-9 (tests).        */
+/* ------------------------------------------------------------------------ */
+double hfo_bf16(double x) {
+  if (x == 0.0 || !isfinite(x)) return x;
+  int e;
+  double f = frexp(x, &e); /* |f| in [0.5, 1) */
+  return ldexp(nearbyint(f * 256.0), e - 8);
+}
+
+double hfo_e4m3_decode(uint8_t c) {
+  int sign = c >> 7, E = (c >> 3) & 15, m = c & 7;
+  double v;
+  if ((c & 0x7F) == 0x7F) return NAN;
+  if (E == 0)
+    v = ldexp((double)m, -9);
+  else
+    v = ldexp(1.0 + m / 8.0, E - 7);
+  return sign ? -v : v;
+}
+
+uint8_t hfo_e4m3_encode(float y) {
+  uint8_t sign = signbit(y) ? 0x80 : 0;
+  double a = fabs((double)y);
+  int best = 0;
+  double berr = INFINITY;
+  for (int c = 0; c <= 0x7E; ++c) {
+    double err = fabs(hfo_e4m3_decode((uint8_t)c) - a);
+    if (err < berr || (err == berr && (c & 1) == 0)) {
+      berr = err;
+      best = c;
+    }
+  }
+  if (a >= 448.0) best = 0x7E;
+  return (uint8_t)(sign | best);
+}
+
+float hfo_fp8_scale(const void *x, int32_t dtype, int64_t row, int32_t d) {
+  float m = 0.0f;
+  for (int32_t i = 0; i < d; ++i) {
+    float v = (float)fabs(val(x, dtype, row * d + i));
+    if (v > m) m = v;
+  }
+  return m > 0.0f ? m / 448.0f : 1.0f;
+}
+
+/* Emulated low-precision inner product of query row q and data row r. */
+static double lowprec_dot(const void *Q, const void *X, int32_t dtype, int64_t q, int64_t r,
+                          int32_t d, int32_t prec) {
+  double acc = 0.0;
+  if (prec == 1) {
+    for (int32_t i = 0; i < d; ++i)
+      acc += hfo_bf16(val(Q, dtype, q * d + i)) * hfo_bf16(val(X, dtype, r * d + i));
+    return acc;
+  }
+  float sq = hfo_fp8_scale(Q, dtype, q, d), sx = hfo_fp8_scale(X, dtype, r, d);
+  for (int32_t i = 0; i < d; ++i) {
+    double a = hfo_e4m3_decode(hfo_e4m3_encode((float)val(Q, dtype, q * d + i) / sq));
+    double b = hfo_e4m3_decode(hfo_e4m3_encode((float)val(X, dtype, r * d + i) / sx));
+    acc += a * b;
+  }
+  return (double)sq * (double)sx * acc;
+}
+
+/* Final selection of the precision form for one query: E scored in the     */
+/* emulated precision, the first S by (score desc, position asc) survive,   */
+/* then FP64 scores of the survivors give the top-k (score desc, pos asc).   */
+void hfo_search_lowprec(const void *X, int32_t dtype, int64_t N, int32_t d, const uint32_t *pos2id,
+                        const uint32_t *c2, const int32_t *c2n, int32_t k2, const void *Q, int64_t nq,
+                        int32_t h, int32_t k, int32_t prec, int32_t S, int32_t *ids, double *scores,
+                        uint32_t *surv_pos, double *surv_score) {
+#pragma omp parallel
+  {
+    uint8_t *mark = (uint8_t *)calloc((size_t)N, 1);
+    cand *E = (cand *)malloc(sizeof(cand) * (size_t)((int64_t)k2 * (2 * h + 1) + 1));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nq; ++q) {
+      int64_t ne = 0;
+      for (int32_t i = 0; i < c2n[q]; ++i) {
+        int64_t r = c2[q * k2 + i], a = r - h < 0 ? 0 : r - h, z = r + h > N - 1 ? N - 1 : r + h;
+        for (int64_t x = a; x <= z; ++x)
+          if (!mark[x]) {
+            mark[x] = 1;
+            E[ne++].r = x;
+          }
+      }
+      for (int64_t i = 0; i < ne; ++i) mark[E[i].r] = 0;
+      for (int64_t i = 0; i < ne; ++i) E[i].s = lowprec_dot(Q, X, dtype, q, (int64_t)pos2id[E[i].r], d, prec);
+      qsort(E, (size_t)ne, sizeof(cand), cmp_score_desc_pos);
+      int64_t ns = ne < S ? ne : S;
+      for (int32_t i = 0; i < S; ++i) {
+        surv_pos[q * S + i] = i < ns ? (uint32_t)E[i].r : 0xFFFFFFFFu;
+        surv_score[q * S + i] = i < ns ? E[i].s : -INFINITY;
+      }
+      for (int64_t i = 0; i < ns; ++i) {
+        int64_t row = (int64_t)pos2id[E[i].r];
+        double acc = 0.0;
+        for (int32_t j = 0; j < d; ++j) acc += val(Q, dtype, q * d + j) * val(X, dtype, row * d + j);
+        E[i].s = acc;
+      }
+      qsort(E, (size_t)ns, sizeof(cand), cmp_score_desc_pos);
+      for (int32_t i = 0; i < k; ++i) {
+        ids[q * k + i] = i < ns ? (int32_t)pos2id[E[i].r] : -1;
+        scores[q * k + i] = i < ns ? E[i].s : -INFINITY;
+      }
+    }
+    free(mark);
+    free(E);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* k-NN graph rows (Alg. 2), for selected rows p only:                       */
 /*   C1(p) = union over orders t of order_t[i-w .. i+w] without p, i being   */
 /*           p's rank in order t (window clipped to the array);              */

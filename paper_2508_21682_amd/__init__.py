@@ -28,7 +28,8 @@ EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_qu
            "hf_hilbert_sort", "hf_srp_sketch", "hf_build_forest", "hf_forest_free",
            "hf_forest_get_info", "hf_forest_perm", "hf_forest_nodes", "hf_forest_pos2id",
            "hf_forest_sketches", "hf_search", "hf_search_debug", "hf_knn_graph",
-           "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name"]
+           "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name", "hf_forest_add_precision",
+           "hf_search_lowprec_debug", "hf_audit_scores"]
 N_STAGES = 12
 
 
@@ -95,6 +96,9 @@ def lib():
             "hf_timing_enable": (C.c_int, [i32]),
             "hf_timing_read": (C.c_int, [P, P]),
             "hf_timing_stage_name": (C.c_char_p, [i32]),
+            "hf_forest_add_precision": (C.c_int, [P, C.c_int, P]),
+            "hf_search_lowprec_debug": (C.c_int, [P, P, C.c_int, i64, P, P, P, P, P, P]),
+            "hf_audit_scores": (C.c_int, [P, C.c_int, i64, i32, P, i64, P, i32, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -266,6 +270,23 @@ class Forest:
                                _stream()))
         return ids, sc
 
+    def add_precision(self, precision: str):
+        _check(lib().hf_forest_add_precision(self._h, HF_PREC[precision], _stream()))
+
+    def search_lowprec_debug(self, q, k: int, k1: int, k2: int, h: int, precision: str, survivors: int = 0):
+        q = _dev(q)
+        t = _torch()
+        nq = q.shape[0]
+        S = survivors or 4 * k
+        ids = _empty((nq, k), t.int32, q)
+        sc = _empty((nq, k), t.float32, q)
+        sp = _empty((nq, S), t.int32, q)
+        ss = _empty((nq, S), t.float32, q)
+        p = self._params(k, k1, k2, h, precision, survivors)
+        _check(lib().hf_search_lowprec_debug(self._h, _ptr(q), _dtype(q), nq, C.byref(p), _ptr(ids), _ptr(sc),
+                                             _ptr(sp), _ptr(ss), _stream()))
+        return dict(ids=ids, scores=sc, surv_pos=sp, surv_score=ss)
+
     def search_debug(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32",
                      survivors: int = 0):
         q = _dev(q)
@@ -281,6 +302,15 @@ class Forest:
         _check(lib().hf_search_debug(self._h, _ptr(q), _dtype(q), nq, C.byref(p), _ptr(ids), _ptr(sc),
                                      _ptr(win), _ptr(c2), _ptr(c2n), _ptr(en), _stream()))
         return dict(ids=ids, scores=sc, winstart=win, c2=c2, c2n=c2n, en=en)
+
+
+def audit_scores(x, q, ids):
+    """FP64 inner products of each query with the rows its ids name (GPU audit kernel)."""
+    x, q, ids = _dev(x), _dev(q), _dev(ids)
+    out = _empty(tuple(ids.shape), _torch().float64, x)
+    _check(lib().hf_audit_scores(_ptr(x), _dtype(x), x.shape[0], x.shape[1], _ptr(q), q.shape[0], _ptr(ids),
+                                 ids.shape[1], _ptr(out), _stream()))
+    return out
 
 
 # ---------------------------------------------------------------- graph

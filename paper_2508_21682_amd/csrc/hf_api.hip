@@ -82,7 +82,8 @@ void make_curves(uint64_t seed, int T, int d, int32_t* perm, uint8_t* refl) {
 
 hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_search_params& p,
                         int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
-                        int32_t* c2n_out, int32_t* en_out, hipStream_t s);
+                        int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
+                        hipStream_t s);
 hf_status graph_launch(const void* X, hf_dtype dt, int64_t N, int d, const hf_graph_params& p,
                        int e, int32_t* ids, float* scores, hipStream_t s);
 
@@ -138,7 +139,8 @@ hf_status data_exp(const void* X, hf_dtype dt, int64_t n, int32_t want, int* e, 
 
 void forest_release(hf_forest* f) {
   if (!f) return;
-  void* ptrs[] = {f->X_pos, f->sk_pos, f->pos2id, f->tree_perm, f->nodes, f->curve_perm, f->curve_refl};
+  void* ptrs[] = {f->X_pos, f->sk_pos, f->pos2id, f->tree_perm, f->nodes, f->curve_perm, f->curve_refl,
+                  f->X_bf16, f->X_fp8, f->s_fp8};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   f->magic = 0;
@@ -472,9 +474,18 @@ static hf_status check_search(const hf_forest* f, const void* Q, hf_dtype dtype,
   HF_ARG(p->k1 >= 1, "k1 must be >= 1");
   HF_ARG(p->k2 >= p->k && p->k2 <= 4096, "k2 must be in [k, 4096]");
   HF_ARG(p->h <= 1024, "h must be <= 1024");
+  HF_ARG(p->precision <= HF_PREC_FP8, "bad precision %u", p->precision);
+  if (p->precision == HF_PREC_BF16 && !f->X_bf16) {
+    set_error("the forest has no BF16 copy: call hf_forest_add_precision first");
+    return HF_ERR_INVALID_ARG;
+  }
+  if (p->precision == HF_PREC_FP8 && !f->X_fp8) {
+    set_error("the forest has no FP8 copy: call hf_forest_add_precision first");
+    return HF_ERR_INVALID_ARG;
+  }
   if (p->precision != HF_PREC_FP32) {
-    set_error("precision %u not built yet", p->precision);
-    return HF_ERR_UNSUPPORTED;
+    const uint32_t S = p->survivors ? p->survivors : 4 * p->k;
+    HF_ARG(S >= p->k && S <= 4096, "survivors must be in [k, 4096]");
   }
   if ((int64_t)f->T * (int64_t)std::min<int64_t>(p->k1, f->N) > (1ll << 30)) {
     set_error("n_trees * k1 too large");
@@ -488,7 +499,7 @@ hf_status hf_search(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64
   clear_error();
   HF_TRY(check_search(f, Q_dev, dtype, nq, params, ids_dev, scores_dev));
   return search_launch(f, Q_dev, nq, *params, ids_dev, scores_dev, nullptr, nullptr, nullptr, nullptr,
-                       (hipStream_t)stream);
+                       nullptr, nullptr, (hipStream_t)stream);
 }
 
 hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64_t nq,
@@ -498,7 +509,34 @@ hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype,
   clear_error();
   HF_TRY(check_search(f, Q_dev, dtype, nq, params, ids_dev, scores_dev));
   return search_launch(f, Q_dev, nq, *params, ids_dev, scores_dev, win_dev, c2_dev, c2n_dev, en_dev,
-                       (hipStream_t)stream);
+                       nullptr, nullptr, (hipStream_t)stream);
+}
+
+hf_status hf_forest_add_precision(hf_forest* f, hf_precision prec, void* stream) {
+  clear_error();
+  HF_TRY(check_forest(f));
+  HF_ARG(prec == HF_PREC_BF16 || prec == HF_PREC_FP8, "precision must be BF16 or FP8");
+  return make_lowprec(f, prec, (hipStream_t)stream);
+}
+
+hf_status hf_search_lowprec_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64_t nq,
+                                  const hf_search_params* params, int32_t* ids_dev, float* scores_dev,
+                                  uint32_t* surv_pos_dev, float* surv_score_dev, void* stream) {
+  clear_error();
+  HF_TRY(check_search(f, Q_dev, dtype, nq, params, ids_dev, scores_dev));
+  HF_ARG(params->precision != HF_PREC_FP32, "precision must be BF16 or FP8");
+  HF_ARG(surv_pos_dev && surv_score_dev, "null pointer");
+  return search_launch(f, Q_dev, nq, *params, ids_dev, scores_dev, nullptr, nullptr, nullptr, nullptr,
+                       surv_pos_dev, surv_score_dev, (hipStream_t)stream);
+}
+
+hf_status hf_audit_scores(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const void* Q_dev,
+                          int64_t nq, const int32_t* ids_dev, int32_t k, double* out_dev, void* stream) {
+  clear_error();
+  HF_ARG(X_dev && Q_dev && ids_dev && out_dev, "null pointer");
+  HF_ARG(valid_dtype(dtype), "bad dtype");
+  HF_ARG(N >= 1 && d >= 1 && d <= 4096 && nq >= 1 && k >= 1, "bad sizes");
+  return audit_launch(X_dev, dtype, d, Q_dev, nq, ids_dev, k, out_dev, (hipStream_t)stream);
 }
 
 hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const hf_graph_params* p,

@@ -206,6 +206,14 @@ struct StageTimer {
   StageTimer(int stage, hipStream_t stream) : st(stage), s(stream) { timing_mark(st, true, s); }
   ~StageTimer() { timing_mark(st, false, s); }
 };
+// hf_lowprec.hip
+hf_status make_lowprec(hf_forest* f, hf_precision prec, hipStream_t s);
+hf_status rerank_lp_launch(const hf_forest* f, hf_precision prec, const void* Qb, int64_t nb,
+                           const uint32_t* c2b, const int32_t* c2nb, int k2, int h, int k, int S,
+                           int32_t* idsb, float* scb, uint32_t* surv_pos, float* surv_score,
+                           int32_t* enb, hipStream_t s);
+hf_status audit_launch(const void* X, hf_dtype dt, int d, const void* Q, int64_t nq, const int32_t* ids,
+                       int k, double* out, hipStream_t s);
 // host helpers (hf_api.hip)
 void make_curves(uint64_t seed, int T, int d, int32_t* perm, uint8_t* refl);
 uint64_t splitmix64_next(uint64_t* state);
@@ -228,6 +236,9 @@ struct hf_forest {
   std::vector<int64_t> node_off;  // T+1 offsets (in nodes)
   int32_t* curve_perm;   // T x d
   uint8_t* curve_refl;   // T x d
+  void* X_bf16;          // N x d bfloat16 copy of X_pos (precision form), or null
+  void* X_fp8;           // N x d e4m3 codes of X_pos, or null
+  float* s_fp8;          // N per-row scales of X_fp8
   int64_t device_bytes;
 };
 constexpr uint32_t HF_FOREST_MAGIC = 0x48464f52u;  // "HFOR"

@@ -16,6 +16,7 @@
 #include <math.h>
 
 #include "hf_internal.h"
+#include "hf_select.h"
 
 namespace hf {
 namespace {
@@ -104,42 +105,6 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
 constexpr int SEL_T = 1024;
 constexpr int CAP = 16384;
 constexpr int NBK = 1024;
-
-__device__ __forceinline__ void bitonic_u32(uint32_t* a, int n2) {
-  for (int k = 2; k <= n2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        int ixj = i ^ j;
-        if (ixj > i) {
-          uint32_t x = a[i], y = a[ixj];
-          bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-}
-
-__device__ __forceinline__ void bitonic_u64(uint64_t* a, int n2) {
-  for (int k = 2; k <= n2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        int ixj = i ^ j;
-        if (ixj > i) {
-          uint64_t x = a[i], y = a[ixj];
-          bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-}
 
 // Visits every window entry of one query: the Hamming values are read 8 at a
 // time (16-byte loads of the query's padded row), the tree position of an
@@ -340,24 +305,6 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
 // ------------------------------------------------------------------ rerank
 constexpr int RR_T = 256;
 
-__device__ __forceinline__ float ordered_to_float(uint32_t o) {
-  uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
-  return __uint_as_float(u);
-}
-
-// Position of expansion entry e: interval i with off[i] <= e < off[i+1].
-__device__ __forceinline__ uint32_t epos(const uint32_t* st, const uint32_t* off, int n2, uint32_t e) {
-  int lo = 0, hi = n2 - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= e)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return st[lo] + (e - off[lo]);
-}
-
 constexpr int RROWS = 4;
 
 // MCH > 0: rows read as 16-byte chunks, MCH chunks per lane; MCH == 0: scalar reads.
@@ -394,36 +341,7 @@ __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64
   for (int i = threadIdx.x; i < k2p; i += RR_T) sc[i] = i < n2 ? c2[q * k2 + i] : NONE32;
   __syncthreads();
   bitonic_u32(sc, k2p);
-  // merged intervals [max(0,r-h), min(N-1,r+h)] of the sorted positions
-  {
-    const int per = (n2 + RR_T - 1) / RR_T;
-    const int a0 = threadIdx.x * per, a1 = min(n2, a0 + per);
-    uint32_t mine = 0;
-    for (int i = a0; i < a1; ++i) {
-      int64_t r = sc[i];
-      int64_t a = r - h < 0 ? 0 : r - h, z = r + h > N - 1 ? N - 1 : r + h;
-      if (i > 0) {
-        int64_t pz = (int64_t)sc[i - 1] + h;
-        pz = pz > N - 1 ? N - 1 : pz;
-        if (a < pz + 1) a = pz + 1;
-      }
-      st[i] = (uint32_t)a;
-      off[i] = z >= a ? (uint32_t)(z - a + 1) : 0u;
-      mine += off[i];
-    }
-    uint32_t tot;
-    uint32_t run = block_excl_scan<RR_T>(mine, scan_tmp, &tot);
-    for (int i = a0; i < a1; ++i) {
-      uint32_t c = off[i];
-      off[i] = run;
-      run += c;
-    }
-    if (threadIdx.x == 0) {
-      off[n2] = tot;
-      s_E = tot;
-    }
-    __syncthreads();
-  }
+  expansion_intervals<RR_T>(sc, n2, h, N, st, off, scan_tmp, &s_E);
   const uint32_t E = s_E;
   // scores: a 16-lane group per row, RROWS consecutive expansion rows in
   // flight per group (mostly adjacent master positions: contiguous reads)
@@ -502,70 +420,8 @@ __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64
     }
   }
   __syncthreads();
-  // radix select of the k-th smallest key
   const uint32_t kk = (uint32_t)min<int64_t>(k, E);
-  if (threadIdx.x == 0) {
-    s_prefix = 0;
-    s_lt = 0;
-  }
-  __syncthreads();
-  uint32_t want = kk;  // rank (1-based) of the threshold key among keys with the prefix
-  for (int pass = 0; pass < 4 && kk > 0; ++pass) {
-    const int shift = 24 - 8 * pass;
-    const uint32_t pmask_hi = pass == 0 ? 0u : (0xFFFFFFFFu << (32 - 8 * pass));
-    const uint32_t prefix = s_prefix;
-    hist[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < E; e += RR_T) {
-      uint32_t key = ekey[e];
-      if ((key & pmask_hi) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t cum = 0;
-      int b = 0;
-      for (; b < 256; ++b) {
-        if (cum + hist[b] >= want) break;
-        cum += hist[b];
-      }
-      s_prefix = prefix | ((uint32_t)b << shift);
-      s_lt += cum;
-      want -= cum;
-    }
-    __syncthreads();
-    want = (want == kk && pass == 0) ? want : want;  // keep registers in sync below
-    if (threadIdx.x == 0) s_eq_need = want;
-    __syncthreads();
-    want = s_eq_need;
-  }
-  const uint32_t thr = s_prefix;
-  const uint32_t n_lt = s_lt;  // keys strictly below the threshold
-  // collect keys < thr, and the first (kk - n_lt) keys == thr in position order
-  if (threadIdx.x == 0) s_nsel = 0;
-  __syncthreads();
-  {
-    const int per = (int)((E + RR_T - 1) / RR_T);
-    const int a0 = threadIdx.x * per, a1 = min((int)E, a0 + per);
-    uint32_t myeq = 0;
-    for (int e = a0; e < a1; ++e) {
-      uint32_t key = ekey[e];
-      if (kk > 0 && key < thr) {
-        uint32_t slot = atomicAdd(&s_nsel, 1u);
-        sel[slot] = ((uint64_t)key << 32) | (uint32_t)e;
-      } else if (kk > 0 && key == thr) {
-        ++myeq;
-      }
-    }
-    uint32_t tot;
-    uint32_t r = block_excl_scan<RR_T>(myeq, scan_tmp, &tot);
-    const uint32_t need_eq = kk - n_lt;
-    for (int e = a0; e < a1; ++e) {
-      if (kk > 0 && ekey[e] == thr) {
-        if (r < need_eq) sel[n_lt + r] = ((uint64_t)thr << 32) | (uint32_t)e;
-        ++r;
-      }
-    }
-  }
+  select_smallest<RR_T>(ekey, E, kk, sel, hist, scan_tmp, &s_prefix, &s_lt, &s_eq_need, &s_nsel);
   __syncthreads();
   for (int i = (int)kk + threadIdx.x; i < kp; i += RR_T) sel[i] = ~0ull;
   __syncthreads();
@@ -590,7 +446,8 @@ __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64
 // ------------------------------------------------------------------ host side
 hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_search_params& p,
                         int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
-                        int32_t* c2n_out, int32_t* en_out, hipStream_t s) {
+                        int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
+                        hipStream_t s) {
   Workspace ws(s);
   const int64_t N = f->N;
   const int d = f->d, T = f->T;
@@ -688,9 +545,16 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
                                               pos_bits, c2 + q0 * k2, c2n + q0);
       HF_LAUNCH_CHECK();
     }
-    {
+    if (p.precision == HF_PREC_FP32) {
       StageTimer tm(ST_RERANK, s);
       HF_TRY(rerank(q0, nb));
+    } else {
+      StageTimer tm(ST_LOWPREC, s);
+      const int S = (int)(p.survivors ? p.survivors : 4 * p.k);
+      HF_TRY(rerank_lp_launch(f, (hf_precision)p.precision, (const char*)Q + q0 * d * esz, nb, c2 + q0 * k2,
+                              c2n + q0, k2, (int)p.h, (int)p.k, S, ids + q0 * p.k, scores + q0 * p.k,
+                              surv_pos ? surv_pos + q0 * S : nullptr, surv_score ? surv_score + q0 * S : nullptr,
+                              en_out ? en_out + q0 : nullptr, s));
     }
   }
   return HF_OK;

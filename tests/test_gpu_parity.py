@@ -247,3 +247,41 @@ def test_graph_parity_ragged(hf, orc):
     _graph_case(hf, orc, x, n=3, w=21, k=7, seed=4, rows=np.arange(333))
     x = datagen.mixture(100, 16, 2, 0.2, 73, dtype=np.float16)
     _graph_case(hf, orc, x, n=2, w=49, k=20, seed=5, rows=np.arange(100))
+
+
+# ------------------------------------------------------------------ precision form
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_precision_form_parity(hf, orc, prec):
+    x, q = datagen.mixture(20000, 384, 64, 0.05, 81, dtype=np.float16, query_seed=82, nq=120)
+    T, M, k1, k2, h, k, S = 4, 100, 300, 100, 2, 30, 120
+    F = orc.build_forest(x, T=T, M=M, seed=5, sketch_seed=6)
+    base = orc.search(F, q, k1, k2, h, k)
+    want = orc.search_lowprec(F, q, base["c2"], base["c2n"], h, k, prec, S)
+    fo = hf.Forest(dev(x), n_trees=T, leaf_max=M, seed=5, sketch_seed=6)
+    fo.add_precision(prec)
+    r = fo.search_lowprec_debug(dev(q), k, k1, k2, h, prec, S)
+    gp, gs = u32(r["surv_pos"]), r["surv_score"].cpu().numpy()
+    fin = np.isfinite(want["surv_score"])
+    assert (np.isfinite(gs) == fin).all()
+    # low-precision scores: exact products, FP32 accumulation
+    assert np.abs(gs[fin] - want["surv_score"][fin]).max() <= TOL
+    # survivor sets agree up to near-ties of the S-th score
+    for i in range(q.shape[0]):
+        a, b = set(gp[i][gp[i] != 0xFFFFFFFF].tolist()), set(want["surv_pos"][i][fin[i]].tolist())
+        if a != b:
+            kth = want["surv_score"][i][fin[i]][-1]
+            for c in a ^ b:
+                j = np.where(want["surv_pos"][i] == c)[0]
+                sc = want["surv_score"][i][j[0]] if j.size else gs[i][np.where(gp[i] == c)[0][0]]
+                assert abs(sc - kth) <= TOL
+    check_topk(r["ids"].cpu().numpy(), r["scores"].cpu().numpy(), want["ids"], want["scores"], x, q, k)
+    fo.free()
+
+
+def test_audit_kernel(hf):
+    x, q = datagen.mixture(5000, 384, 8, 0.05, 83, dtype=np.float16, query_seed=84, nq=50)
+    ids = np.random.default_rng(1).integers(-1, 5000, (50, 7)).astype(np.int32)
+    got = hf.audit_scores(dev(x), dev(q), dev(ids)).cpu().numpy()
+    X, Q = x.astype(np.float64), q.astype(np.float64)
+    want = np.where(ids >= 0, np.einsum("qd,qkd->qk", Q, X[np.maximum(ids, 0)]), 0.0)
+    assert np.abs(got - want).max() <= 1e-12

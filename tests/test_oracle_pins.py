@@ -410,3 +410,33 @@ def test_graph_prefilter_by_hamming(orc):
         C2 = sorted(C1, key=lambda c: (hm[c], c))[:k2]
         cos = {c: X[p] @ X[c] / (np.linalg.norm(X[p]) * np.linalg.norm(X[c])) for c in C2}
         assert ids[ri].tolist() == sorted(C2, key=lambda c: (-cos[c], c))[:k]
+
+
+# ----------------------------------------------------------------- precision emulation
+def test_e4m3_codes_roundtrip_and_extremes(orc):
+    vals = [orc.e4m3_decode(c) for c in range(0x7F)]
+    assert vals[0x7E] == 448.0 and vals[1] == 2.0 ** -9 and vals[8] == 2.0 ** -6
+    assert all(b > a for a, b in zip(vals, vals[1:]))  # positive codes are increasing
+    for c in range(0x7F):
+        assert orc.e4m3_encode(vals[c]) == c
+        assert orc.e4m3_encode(-vals[c]) == (c | 0x80 if c else 0x80)
+    # midpoints go to the even code, beyond 448 saturates
+    for c in range(0x7E):
+        mid = (vals[c] + vals[c + 1]) / 2
+        assert orc.e4m3_encode(mid) == (c if c % 2 == 0 else c + 1)
+    assert orc.e4m3_encode(1e6) == 0x7E and orc.e4m3_encode(-500.0) == 0xFE
+
+
+def test_bf16_rounding_against_bit_arithmetic(orc):
+    import struct
+
+    rng = np.random.default_rng(9)
+    xs = np.concatenate([rng.standard_normal(2000), [1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -1.5, 2.0 ** -20]])
+    for x in xs.astype(np.float16).astype(np.float64):
+        u = struct.unpack("<I", struct.pack("<f", x))[0]
+        lo = u & 0xFFFF
+        hi = u >> 16
+        if lo > 0x8000 or (lo == 0x8000 and (hi & 1)):
+            hi += 1
+        want = struct.unpack("<f", struct.pack("<I", hi << 16))[0]
+        assert orc.bf16(float(x)) == want

@@ -246,8 +246,56 @@ def bench_search(args, hf, torch, ws):
             res["forms"][prec] = form
             log("form %s: recall %.4f, %.0f QPS, low-precision score error max %.3g" % (
                 prec, form["recall"], form["qps"], lp_err["max_abs"]))
+    if args.learned:
+        res.setdefault("forms", {})["learned"] = bench_learned(args, hf, torch, ws, forest, x, q, gt, nq)
     forest.free()
     return res
+
+
+def bench_learned(args, hf, torch, ws, forest, x, q, gt, nq):
+    """Learned sketches: the MLP hash trained by libhf on (training query, true
+    neighbour) pairs from an exact GPU brute force, then used as the forest's
+    sketches at the same (k1, k2, h); SRP is restored afterwards."""
+    import datagen
+    import numpy as np
+
+    ntr, kn = args.learned_queries, args.learned_nn
+    qt = datagen.mixture_device(ntr, ws["d"], ws["n_comp"], ws["sigma"], ws["seed"], ws["unit"], draw_seed=2513)
+    log("learned hash: ground truth of %d training queries" % ntr)
+    nn = ground_truth_ip(x, qt, kn).cpu().numpy()
+    e = forest.info["quant_exp"]
+    qi, pi = hf.hilbert_pairs(hf.quantize(qt, e), nn, 5, args.learned_batch)
+    A = qt[torch.from_numpy(qi).to(x.device)].contiguous()
+    B = x[torch.from_numpy(pi).to(x.device)].contiguous()
+    L = hf.LHash.init(ws["d"], 256, seed=7)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    curve = L.train(A, B, hf.train_params(epochs=args.learned_epochs, batch=args.learned_batch, lr=1e-3, tau=0.1,
+                                          slope=2.0, balance=0.05, keep_blocks=True))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    log("learned hash trained on %d pairs in %.2f s, loss per epoch %s" % (A.shape[0], train_s, np.round(curve, 3)))
+    t = time.perf_counter()
+    forest.set_sketch("learned", L)
+    torch.cuda.synchronize()
+    enc_s = time.perf_counter() - t
+    forest.search(q, args.k, args.k1, args.k2, args.h)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        lid, _ = forest.search(q, args.k, args.k1, args.k2, args.h)
+    torch.cuda.synchronize()
+    ldt = time.perf_counter() - t
+    lrec = recall(lid, gt)
+    forest.set_sketch("srp")
+    srid, _ = forest.search(q, args.k, args.k1, args.k2, args.h)
+    srec = recall(srid, gt)
+    log("learned sketches: recall %.4f vs SRP %.4f at k1=%d k2=%d h=%d" % (lrec, srec, args.k1, args.k2, args.h))
+    L.free()
+    return {"recall": lrec, "recall_srp_same_budget": srec, "gain_over_srp": lrec - srec,
+            "qps": nq * args.steps / ldt, "train_pairs": int(A.shape[0]), "train_s": train_s,
+            "encode_23M_s": enc_s, "loss_per_epoch": [float(v) for v in curve],
+            "sketch_in_use": "srp" if lrec <= srec else "learned"}
 
 
 def bench_graph(args, hf, torch, ws):
@@ -319,6 +367,11 @@ def main():
     ap.add_argument("--window", type=int, default=32)
     ap.add_argument("--sweep", default=None, help="extra search configs 'k1,k2,h;k1,k2,h'")
     ap.add_argument("--forms", default="bf16,fp8", help="precision forms measured after the plain search")
+    ap.add_argument("--learned", type=int, default=1, help="also train and measure the learned sketch form")
+    ap.add_argument("--learned-queries", type=int, default=20000)
+    ap.add_argument("--learned-nn", type=int, default=30)
+    ap.add_argument("--learned-batch", type=int, default=500)
+    ap.add_argument("--learned-epochs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration for rocprofv3)")

@@ -233,6 +233,56 @@ hf_status hf_search_lowprec_debug(const hf_forest* f, const void* Q_dev, hf_dtyp
 hf_status hf_audit_scores(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const void* Q_dev,
                           int64_t nq, const int32_t* ids_dev, int32_t k, double* out_dev, void* stream);
 
+/* ------------------------------------------------------------ learned hash */
+
+/* Learned hash (not in the paper): sketch bit j of x = [z2_j >= 0] with
+ * z1 = W1 bf16(x) + b1, a = bf16(relu(z1)), z2 = W2 a + b2 (BF16 weights and
+ * inputs on MFMA, FP32 accumulate).  W1 is hidden x d, W2 is 512 x hidden,
+ * row-major, given as FP32 host arrays (the master copy trained by
+ * hf_lhash_train).  Handle from hf_lhash_create, freed by hf_lhash_free; it
+ * must outlive any forest using it (hf_forest_set_sketch). */
+typedef struct hf_lhash_train_params {
+  uint32_t struct_size;
+  uint32_t epochs;        /* passes over the pairs */
+  uint32_t batch;         /* pairs per step, 2..8192 (in-batch negatives) */
+  float lr, weight_decay; /* AdamW (decoupled decay on W1, W2) */
+  float beta1, beta2, eps;
+  float slope;            /* codes c = tanh(slope * z2) */
+  float tau;              /* InfoNCE temperature on <c_q, c_p> / 512 */
+  float balance;          /* weight of sum_b (mean_b c)^2 */
+  uint32_t keep_blocks;   /* 0: shuffle all pairs each epoch; 1: batches are the
+                             contiguous blocks of the given pair order (only the
+                             order of the blocks is shuffled), so a caller that
+                             orders pairs along a Hilbert order gets spatial
+                             neighbours as in-batch negatives */
+  uint64_t seed;          /* shuffles the pairs (or blocks) each epoch */
+} hf_lhash_train_params;
+
+hf_status hf_lhash_create(int32_t d, int32_t hidden, const float* W1_host, const float* b1_host,
+                          const float* W2_host, const float* b2_host, hf_lhash** out);
+void hf_lhash_free(hf_lhash* h);
+/* Current FP32 master weights (synchronises). */
+hf_status hf_lhash_get(const hf_lhash* h, float* W1_host, float* b1_host, float* W2_host, float* b2_host);
+/* 512-bit learned sketches of N rows (N x 8 uint64, bit j in word j/64 at j%64). */
+hf_status hf_lhash_encode(const hf_lhash* h, const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
+                          uint64_t* sk_dev, void* stream);
+/* Loss (host) and FP32 gradients (device, shapes of W1, b1, W2, b2) of the
+ * training objective on one batch of npairs positive pairs (A_dev[i], B_dev[i]):
+ * (1/B) sum_i [log sum_j exp(S_ij/tau) - S_ii/tau] + balance * sum_b m_b^2,
+ * S_ij = <c(A_i), c(B_j)> / 512, m = mean code over the 2B rows.  Synchronises. */
+hf_status hf_lhash_grad(const hf_lhash* h, const void* A_dev, const void* B_dev, hf_dtype dtype,
+                        int64_t npairs, int32_t d, const hf_lhash_train_params* params, float* loss_host,
+                        float* gW1_dev, float* gb1_dev, float* gW2_dev, float* gb2_dev, void* stream);
+/* AdamW training on npairs pairs (rows of A_dev and B_dev), `epochs` passes of
+ * shuffled batches; loss_curve_host (nullable) receives the mean loss of each
+ * epoch.  Synchronises. */
+hf_status hf_lhash_train(hf_lhash* h, const void* A_dev, const void* B_dev, hf_dtype dtype, int64_t npairs,
+                         int32_t d, const hf_lhash_train_params* params, float* loss_curve_host, void* stream);
+/* Replaces the forest's sketches: HF_SKETCH_SRP (from its sketch_seed) or
+ * HF_SKETCH_LEARNED (lhash encodes the master-ordered rows, and queries at
+ * search time).  Synchronises. */
+hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash* lhash, void* stream);
+
 /* ------------------------------------------------------------------ timing */
 
 /* Per-kernel timing with hipEvents recorded on the caller's stream around

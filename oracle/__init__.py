@@ -65,6 +65,9 @@ def lib():
             "hfo_e4m3_decode": (C.c_double, [C.c_uint8]),
             "hfo_e4m3_encode": (C.c_uint8, [C.c_float]),
             "hfo_fp8_scale": (C.c_float, [P, i32, i64, i32]),
+            "hfo_mlp_forward": (None, [P, i32, i64, i32, i32, P, P, P, P, i32, P, P, P, P]),
+            "hfo_lhash_grad": (C.c_double, [P, P, i32, i64, i32, i32, P, P, P, P, C.c_double, C.c_double,
+                                            C.c_double, i32, P, P, P, P]),
             "hfo_search_lowprec": (None, [P, i32, i64, i32, P, P, P, i32, P, i64, i32, i32, i32, i32,
                                           P, P, P, P]),
         }
@@ -271,6 +274,33 @@ def e4m3_decode(c: int) -> float:
 
 def e4m3_encode(y: float) -> int:
     return int(lib().hfo_e4m3_encode(y))
+
+
+def mlp_forward(x, W1, b1, W2, b2, rounded=True):
+    """Learned-hash forward in FP64: (z1, a, z2, band) with band = fragile margin of z2."""
+    x = np.ascontiguousarray(x)
+    n, d = x.shape
+    hid = W1.shape[0]
+    f = lambda a: np.ascontiguousarray(a, np.float32)
+    W1, b1, W2, b2 = f(W1), f(b1), f(W2), f(b2)
+    z1 = np.empty((n, hid)); a = np.empty((n, hid)); z2 = np.empty((n, 512)); band = np.empty((n, 512))
+    lib().hfo_mlp_forward(_p(x), _dtype_code(x), n, d, hid, _p(W1), _p(b1), _p(W2), _p(b2), int(rounded),
+                          _p(z1), _p(a), _p(z2), _p(band))
+    return z1, a, z2, band
+
+
+def lhash_grad(A, B, W1, b1, W2, b2, slope, tau, lam, rounded=True):
+    """Loss and FP64 gradients of the learned-hash training objective on one batch of pairs."""
+    A = np.ascontiguousarray(A)
+    Bm = np.ascontiguousarray(B.astype(A.dtype))
+    n, d = A.shape
+    hid = W1.shape[0]
+    f = lambda a: np.ascontiguousarray(a, np.float32)
+    W1, b1, W2, b2 = f(W1), f(b1), f(W2), f(b2)
+    g = [np.empty((hid, d)), np.empty(hid), np.empty((512, hid)), np.empty(512)]
+    loss = lib().hfo_lhash_grad(_p(A), _p(Bm), _dtype_code(A), n, d, hid, _p(W1), _p(b1), _p(W2), _p(b2),
+                                slope, tau, lam, int(rounded), *[_p(v) for v in g])
+    return float(loss), g
 
 
 # --------------------------------------------------------------------------- Alg. 2

@@ -626,6 +626,150 @@ void hfo_search_lowprec(const void *X, int32_t dtype, int64_t N, int32_t d, cons
 }
 
 /* ------------------------------------------------------------------------ */
+/* Learned hash (not in the paper), FP64.                                    */
+/*   z1 = W1 r(x) + b1, a = r(relu(z1)), z2 = W2 a + b2, bit j = [z2_j >= 0] */
+/* with r() = bf16 rounding of inputs, weights and hidden activations when   */
+/* `rounded` is set (the deployed network), identity otherwise.  W1 is      */
+/* hidden x d, W2 is 512 x hidden, row-major.                                */
+/* Training loss over B pairs (q_i, p_i), codes c = tanh(slope * z2):        */
+/*   S_ij = <c(q_i), c(p_j)> / 512,                                          */
+/*   L = (1/B) sum_i [ log sum_j exp(S_ij / tau) - S_ii / tau ]              */
+/*       + lambda * sum_b m_b^2,  m_b = mean of c_b over all 2B codes.       */
+/* Gradients by hand (chain rule, rounding treated as identity).             */
+/* Pinned: central finite differences with rounded = 0 (tests).             */
+/* ------------------------------------------------------------------------ */
+static double rb(double x, int rounded) { return rounded ? hfo_bf16(x) : x; }
+
+/* band_out (nullable): margin below which the sign of z2 may differ from an
+ * FP32-accumulating implementation.  Sums of K products in FP32 differ from
+ * the FP64 value by at most about (K/32 + 5) * 2^-24 * sum|terms|; 2^-16 *
+ * sum|terms| bounds that for K <= 4096.  A hidden activation can then round to
+ * a different bf16 value only if z1 lies within that bound of a rounding
+ * boundary (or of 0, the relu kink); such activations may move by one bf16
+ * step (or all of a), which moves z2_j by |W2[j][i]| times that. */
+void hfo_mlp_forward(const void *x, int32_t dtype, int64_t n, int32_t d, int32_t hid,
+                     const float *W1, const float *b1, const float *W2, const float *b2,
+                     int32_t rounded, double *z1_out, double *a_out, double *z2_out,
+                     double *band_out) {
+#pragma omp parallel
+  {
+    double *move = (double *)malloc(sizeof(double) * hid);
+#pragma omp for schedule(static)
+    for (int64_t r = 0; r < n; ++r) {
+      double *z1 = z1_out + r * hid, *a = a_out + r * hid;
+      for (int32_t j = 0; j < hid; ++j) {
+        double acc = 0.0, mag = fabs((double)b1[j]);
+        for (int32_t i = 0; i < d; ++i) {
+          double t = rb(W1[(int64_t)j * d + i], rounded) * rb(val(x, dtype, r * d + i), rounded);
+          acc += t;
+          mag += fabs(t);
+        }
+        z1[j] = acc + b1[j];
+        a[j] = rb(z1[j] > 0.0 ? z1[j] : 0.0, rounded);
+        double delta = ldexp(mag, -16);
+        move[j] = 0.0;
+        if (fabs(z1[j]) <= delta) {
+          move[j] = fabs(a[j]) + delta; /* relu kink: a may be 0 or a small value */
+        } else if (z1[j] > 0.0 && rounded) {
+          int e;
+          frexp(a[j], &e);
+          double u = ldexp(1.0, e - 9); /* the smaller of the two spacings around a */
+          double lo_mid = a[j] - u / 2, hi_mid = a[j] + ldexp(1.0, e - 8) / 2;
+          if (fabs(z1[j] - lo_mid) <= delta || fabs(z1[j] - hi_mid) <= delta) move[j] = ldexp(1.0, e - 8);
+        }
+      }
+      for (int32_t j = 0; j < 512; ++j) {
+        double acc = 0.0, mag = fabs((double)b2[j]), mv = 0.0;
+        for (int32_t i = 0; i < hid; ++i) {
+          double w = rb(W2[(int64_t)j * hid + i], rounded);
+          acc += w * a[i];
+          mag += fabs(w * a[i]);
+          mv += fabs(w) * move[i];
+        }
+        z2_out[r * 512 + j] = acc + b2[j];
+        if (band_out) band_out[r * 512 + j] = mv + ldexp(mag, -16);
+      }
+    }
+    free(move);
+  }
+}
+
+double hfo_lhash_grad(const void *A, const void *Bm, int32_t dtype, int64_t B, int32_t d, int32_t hid,
+                      const float *W1, const float *b1, const float *W2, const float *b2, double slope,
+                      double tau, double lambda, int32_t rounded, double *gW1, double *gb1, double *gW2,
+                      double *gb2) {
+  const int64_t R = 2 * B; /* rows: the B queries, then the B positives */
+  double *z1 = (double *)malloc(sizeof(double) * R * hid);
+  double *a = (double *)malloc(sizeof(double) * R * hid);
+  double *z2 = (double *)malloc(sizeof(double) * R * 512);
+  double *c = (double *)malloc(sizeof(double) * R * 512);
+  double *dc = (double *)calloc((size_t)(R * 512), sizeof(double));
+  double *S = (double *)malloc(sizeof(double) * B * B);
+  double *m = (double *)calloc(512, sizeof(double));
+  hfo_mlp_forward(A, dtype, B, d, hid, W1, b1, W2, b2, rounded, z1, a, z2, NULL);
+  hfo_mlp_forward(Bm, dtype, B, d, hid, W1, b1, W2, b2, rounded, z1 + B * hid, a + B * hid, z2 + B * 512, NULL);
+  for (int64_t i = 0; i < R * 512; ++i) c[i] = tanh(slope * z2[i]);
+  double loss = 0.0;
+  for (int64_t i = 0; i < B; ++i)
+    for (int64_t j = 0; j < B; ++j) {
+      double acc = 0.0;
+      for (int32_t b = 0; b < 512; ++b) acc += c[i * 512 + b] * c[(B + j) * 512 + b];
+      S[i * B + j] = acc / 512.0;
+    }
+  for (int64_t i = 0; i < B; ++i) {
+    double mx = -INFINITY, sum = 0.0;
+    for (int64_t j = 0; j < B; ++j) mx = fmax(mx, S[i * B + j] / tau);
+    for (int64_t j = 0; j < B; ++j) sum += exp(S[i * B + j] / tau - mx);
+    loss += (mx + log(sum) - S[i * B + i] / tau) / (double)B;
+    for (int64_t j = 0; j < B; ++j) {
+      double g = (exp(S[i * B + j] / tau - mx) / sum - (i == j ? 1.0 : 0.0)) / (tau * (double)B);
+      for (int32_t b = 0; b < 512; ++b) {
+        dc[i * 512 + b] += g * c[(B + j) * 512 + b] / 512.0;
+        dc[(B + j) * 512 + b] += g * c[i * 512 + b] / 512.0;
+      }
+    }
+  }
+  for (int64_t r = 0; r < R; ++r)
+    for (int32_t b = 0; b < 512; ++b) m[b] += c[r * 512 + b] / (double)R;
+  for (int32_t b = 0; b < 512; ++b) loss += lambda * m[b] * m[b];
+  for (int64_t r = 0; r < R; ++r)
+    for (int32_t b = 0; b < 512; ++b) dc[r * 512 + b] += lambda * 2.0 * m[b] / (double)R;
+  memset(gW1, 0, sizeof(double) * hid * d);
+  memset(gb1, 0, sizeof(double) * hid);
+  memset(gW2, 0, sizeof(double) * 512 * hid);
+  memset(gb2, 0, sizeof(double) * 512);
+  double *dz1 = (double *)malloc(sizeof(double) * hid);
+  for (int64_t r = 0; r < R; ++r) {
+    const void *src = r < B ? A : Bm;
+    int64_t rr = r < B ? r : r - B;
+    for (int32_t i = 0; i < hid; ++i) dz1[i] = 0.0;
+    for (int32_t j = 0; j < 512; ++j) {
+      double cj = c[r * 512 + j];
+      double dz2 = dc[r * 512 + j] * slope * (1.0 - cj * cj);
+      gb2[j] += dz2;
+      for (int32_t i = 0; i < hid; ++i) {
+        gW2[(int64_t)j * hid + i] += dz2 * a[r * hid + i];
+        dz1[i] += dz2 * rb(W2[(int64_t)j * hid + i], rounded);
+      }
+    }
+    for (int32_t i = 0; i < hid; ++i) {
+      double g = z1[r * hid + i] > 0.0 ? dz1[i] : 0.0;
+      gb1[i] += g;
+      for (int32_t k = 0; k < d; ++k) gW1[(int64_t)i * d + k] += g * rb(val(src, dtype, rr * d + k), rounded);
+    }
+  }
+  free(dz1);
+  free(z1);
+  free(a);
+  free(z2);
+  free(c);
+  free(dc);
+  free(S);
+  free(m);
+  return loss;
+}
+
+/* ------------------------------------------------------------------------ */
 /* k-NN graph rows (Alg. 2), for selected rows p only:                       */
 /*   C1(p) = union over orders t of order_t[i-w .. i+w] without p, i being   */
 /*           p's rank in order t (window clipped to the array);              */

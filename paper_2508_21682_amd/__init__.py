@@ -29,7 +29,8 @@ EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_qu
            "hf_forest_get_info", "hf_forest_perm", "hf_forest_nodes", "hf_forest_pos2id",
            "hf_forest_sketches", "hf_search", "hf_search_debug", "hf_knn_graph",
            "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name", "hf_forest_add_precision",
-           "hf_search_lowprec_debug", "hf_audit_scores"]
+           "hf_search_lowprec_debug", "hf_audit_scores", "hf_lhash_create", "hf_lhash_free", "hf_lhash_get",
+           "hf_lhash_encode", "hf_lhash_grad", "hf_lhash_train", "hf_forest_set_sketch"]
 N_STAGES = 12
 
 
@@ -56,6 +57,33 @@ class GraphParams(C.Structure):
                 ("k", C.c_uint32), ("k2", C.c_uint32), ("quant_exp", C.c_int32),
                 ("sketch", C.c_uint32), ("seed", C.c_uint64), ("sketch_seed", C.c_uint64),
                 ("lhash", C.c_void_p)]
+
+
+class LHashTrainParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("epochs", C.c_uint32), ("batch", C.c_uint32),
+                ("lr", C.c_float), ("weight_decay", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("slope", C.c_float), ("tau", C.c_float), ("balance", C.c_float),
+                ("keep_blocks", C.c_uint32), ("seed", C.c_uint64)]
+
+
+def train_params(epochs=5, batch=1024, lr=1e-3, weight_decay=1e-2, slope=1.0, tau=0.1, balance=0.1, seed=7,
+                 keep_blocks=False):
+    return LHashTrainParams(C.sizeof(LHashTrainParams), epochs, batch, lr, weight_decay, 0.9, 0.999, 1e-8,
+                            slope, tau, balance, int(keep_blocks), seed)
+
+
+def hilbert_pairs(q_codes, nn_ids, seed: int, batch: int):
+    """Pair order for training with spatial hard negatives: queries along a
+    Hilbert order, one block per neighbour rank, so a block of `batch`
+    consecutive pairs holds distinct, nearby queries.  Returns (query row,
+    neighbour id) index arrays of the ordered pairs (host)."""
+    order = hilbert_sort(q_codes, seed, 0).cpu().numpy().view(np.uint32).astype(np.int64)
+    nq, kn = nn_ids.shape
+    usable = (nq // batch) * batch
+    order = order[:usable]
+    qi = np.concatenate([order for _ in range(kn)])
+    pi = np.concatenate([nn_ids[order, r] for r in range(kn)])
+    return qi, pi
 
 
 class ForestInfo(C.Structure):
@@ -99,6 +127,13 @@ def lib():
             "hf_forest_add_precision": (C.c_int, [P, C.c_int, P]),
             "hf_search_lowprec_debug": (C.c_int, [P, P, C.c_int, i64, P, P, P, P, P, P]),
             "hf_audit_scores": (C.c_int, [P, C.c_int, i64, i32, P, i64, P, i32, P, P]),
+            "hf_lhash_create": (C.c_int, [i32, i32, P, P, P, P, P]),
+            "hf_lhash_free": (None, [P]),
+            "hf_lhash_get": (C.c_int, [P, P, P, P, P]),
+            "hf_lhash_encode": (C.c_int, [P, P, C.c_int, i64, i32, P, P]),
+            "hf_lhash_grad": (C.c_int, [P, P, P, C.c_int, i64, i32, P, P, P, P, P, P, P]),
+            "hf_lhash_train": (C.c_int, [P, P, P, C.c_int, i64, i32, P, P, P]),
+            "hf_forest_set_sketch": (C.c_int, [P, C.c_int, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -270,6 +305,12 @@ class Forest:
                                _stream()))
         return ids, sc
 
+    def set_sketch(self, kind: str, lhash=None):
+        """'srp' or 'learned' (lhash must outlive the forest's use of it)."""
+        self._lhash = lhash
+        _check(lib().hf_forest_set_sketch(self._h, {"srp": HF_SKETCH_SRP, "learned": HF_SKETCH_LEARNED}[kind],
+                                          None if lhash is None else lhash._h, _stream()))
+
     def add_precision(self, precision: str):
         _check(lib().hf_forest_add_precision(self._h, HF_PREC[precision], _stream()))
 
@@ -311,6 +352,69 @@ def audit_scores(x, q, ids):
     _check(lib().hf_audit_scores(_ptr(x), _dtype(x), x.shape[0], x.shape[1], _ptr(q), q.shape[0], _ptr(ids),
                                  ids.shape[1], _ptr(out), _stream()))
     return out
+
+
+class LHash:
+    """Learned MLP hash d -> hidden -> 512 sign bits, weights trained by libhf's kernels."""
+
+    def __init__(self, W1, b1, W2, b2):
+        f = lambda a: np.ascontiguousarray(a, np.float32)
+        W1, b1, W2, b2 = f(W1), f(b1), f(W2), f(b2)
+        self.hidden, self.d = W1.shape
+        h = C.c_void_p()
+        _check(lib().hf_lhash_create(self.d, self.hidden, *[a.ctypes.data_as(C.c_void_p) for a in (W1, b1, W2, b2)],
+                                     C.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def init(d: int, hidden: int, seed: int):
+        """He-style random initialisation drawn on the host (seeded numpy)."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        W1 = rng.standard_normal((hidden, d)) * np.sqrt(2.0 / d)
+        W2 = rng.standard_normal((512, hidden)) * np.sqrt(1.0 / hidden)
+        return LHash(W1, np.zeros(hidden), W2, np.zeros(512))
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().hf_lhash_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def weights(self):
+        out = [np.empty((self.hidden, self.d), np.float32), np.empty(self.hidden, np.float32),
+               np.empty((512, self.hidden), np.float32), np.empty(512, np.float32)]
+        _check(lib().hf_lhash_get(self._h, *[a.ctypes.data_as(C.c_void_p) for a in out]))
+        return out
+
+    def encode(self, x):
+        x = _dev(x)
+        out = _empty((x.shape[0], 8), _torch().int64, x)
+        _check(lib().hf_lhash_encode(self._h, _ptr(x), _dtype(x), x.shape[0], x.shape[1], _ptr(out), _stream()))
+        return out
+
+    def grad(self, A, B, params):
+        A, B = _dev(A), _dev(B)
+        t = _torch()
+        g = [t.empty((self.hidden, self.d), dtype=t.float32, device=A.device),
+             t.empty(self.hidden, dtype=t.float32, device=A.device),
+             t.empty((512, self.hidden), dtype=t.float32, device=A.device),
+             t.empty(512, dtype=t.float32, device=A.device)]
+        loss = C.c_float()
+        _check(lib().hf_lhash_grad(self._h, _ptr(A), _ptr(B), _dtype(A), A.shape[0], A.shape[1], C.byref(params),
+                                   C.byref(loss), *[_ptr(v) for v in g], _stream()))
+        return float(loss.value), g
+
+    def train(self, A, B, params):
+        A, B = _dev(A), _dev(B)
+        curve = np.zeros(max(1, params.epochs), np.float32)
+        _check(lib().hf_lhash_train(self._h, _ptr(A), _ptr(B), _dtype(A), A.shape[0], A.shape[1], C.byref(params),
+                                    curve.ctypes.data_as(C.c_void_p), _stream()))
+        return curve
 
 
 # ---------------------------------------------------------------- graph

@@ -512,6 +512,25 @@ hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype,
                        nullptr, nullptr, (hipStream_t)stream);
 }
 
+hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash* lhash, void* stream) {
+  clear_error();
+  HF_TRY(check_forest(f));
+  HF_ARG(kind == HF_SKETCH_SRP || kind == HF_SKETCH_LEARNED, "bad sketch kind");
+  hipStream_t s = (hipStream_t)stream;
+  if (kind == HF_SKETCH_LEARNED) {
+    HF_ARG(lhash != nullptr, "learned sketches need a hash");
+    HF_ARG(lhash_dim(lhash) == f->d, "the hash's input size differs from the forest's d");
+    HF_TRY(lhash_encode_dev(lhash, f->X_pos, f->dtype, f->N, f->sk_pos, s));
+  } else {
+    Workspace ws(s);
+    HF_TRY(srp_sketch(f->X_pos, f->dtype, f->N, f->d, f->e, f->sketch_seed, f->sk_pos, ws));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  f->sketch_kind = (int)kind;
+  f->lhash = kind == HF_SKETCH_LEARNED ? lhash : nullptr;
+  return HF_OK;
+}
+
 hf_status hf_forest_add_precision(hf_forest* f, hf_precision prec, void* stream) {
   clear_error();
   HF_TRY(check_forest(f));

@@ -214,6 +214,9 @@ hf_status rerank_lp_launch(const hf_forest* f, hf_precision prec, const void* Qb
                            int32_t* enb, hipStream_t s);
 hf_status audit_launch(const void* X, hf_dtype dt, int d, const void* Q, int64_t nq, const int32_t* ids,
                        int k, double* out, hipStream_t s);
+// hf_lhash.hip
+hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_t N, uint64_t* sk, hipStream_t s);
+int lhash_dim(const hf_lhash* L);
 // host helpers (hf_api.hip)
 void make_curves(uint64_t seed, int T, int d, int32_t* perm, uint8_t* refl);
 uint64_t splitmix64_next(uint64_t* state);
@@ -239,6 +242,8 @@ struct hf_forest {
   void* X_bf16;          // N x d bfloat16 copy of X_pos (precision form), or null
   void* X_fp8;           // N x d e4m3 codes of X_pos, or null
   float* s_fp8;          // N per-row scales of X_fp8
+  int sketch_kind;       // hf_sketch_kind of sk_pos
+  const hf_lhash* lhash; // encoder of queries when sketch_kind is learned (not owned)
   int64_t device_bytes;
 };
 constexpr uint32_t HF_FOREST_MAGIC = 0x48464f52u;  // "HFOR"

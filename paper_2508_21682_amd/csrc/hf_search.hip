@@ -464,7 +464,10 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   }
   {
     StageTimer tm(ST_QSKETCH, s);
-    HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws));
+    if (f->sketch_kind == HF_SKETCH_LEARNED)
+      HF_TRY(lhash_encode_dev(f->lhash, Q, f->dtype, nq, qsk, s));
+    else
+      HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws));
   }
   uint32_t* win = win_out;
   if (!win) HF_TRY(ws.alloc(&win, (size_t)(nq * T)));

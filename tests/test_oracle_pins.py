@@ -440,3 +440,47 @@ def test_bf16_rounding_against_bit_arithmetic(orc):
             hi += 1
         want = struct.unpack("<f", struct.pack("<I", hi << 16))[0]
         assert orc.bf16(float(x)) == want
+
+
+# ----------------------------------------------------------------- learned hash
+def _small_net(seed, d=24, hid=16):
+    rng = np.random.default_rng(seed)
+    W1 = (rng.standard_normal((hid, d)) / np.sqrt(d)).astype(np.float32)
+    b1 = (0.1 * rng.standard_normal(hid)).astype(np.float32)
+    W2 = (rng.standard_normal((512, hid)) / np.sqrt(hid)).astype(np.float32)
+    b2 = (0.1 * rng.standard_normal(512)).astype(np.float32)
+    return W1, b1, W2, b2
+
+
+def test_lhash_forward_is_a_plain_mlp(orc):
+    W1, b1, W2, b2 = _small_net(1)
+    x = np.random.default_rng(2).standard_normal((5, 24)).astype(np.float32)
+    z1, a, z2, _ = orc.mlp_forward(x, W1, b1, W2, b2, rounded=False)
+    X = x.astype(np.float64)
+    ref1 = X @ W1.astype(np.float64).T + b1
+    ref2 = np.maximum(ref1, 0) @ W2.astype(np.float64).T + b2
+    assert np.allclose(z1, ref1, atol=1e-12) and np.allclose(z2, ref2, atol=1e-12)
+
+
+def test_lhash_gradients_match_finite_differences(orc):
+    W1, b1, W2, b2 = _small_net(3)
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((6, 24)).astype(np.float32)
+    B = (A + 0.3 * rng.standard_normal((6, 24))).astype(np.float32)
+    args = dict(slope=2.0, tau=0.2, lam=0.05, rounded=False)
+    loss, g = orc.lhash_grad(A, B, W1, b1, W2, b2, **args)
+    params = [W1, b1, W2, b2]
+    for pi, P in enumerate(params):
+        flat = P.reshape(-1)
+        for idx in rng.choice(flat.size, 6, replace=False):
+            h = 1e-3
+            old = flat[idx]
+            vals = []
+            for sgn in (+1, -1):
+                flat[idx] = old + sgn * h
+                vals.append(orc.lhash_grad(A, B, *params, **args)[0])
+            flat[idx] = old
+            # the float32 parameter holds old+-h exactly only approximately: use the stored step
+            num = (vals[0] - vals[1]) / (np.float64(np.float32(old + h)) - np.float64(np.float32(old - h)))
+            ana = g[pi].reshape(-1)[idx]
+            assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)) + 1e-7, (pi, idx, num, ana)

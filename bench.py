@@ -343,13 +343,20 @@ def bench_graph(args, hf, torch, ws):
         rows = torch.randperm(N, generator=torch.Generator(device="cpu").manual_seed(4))[:10000].to(x.device)
         gt = ground_truth_graph(x, rows, args.k)
         for cfg in args.sweep.split(";"):
-            no, wi = (int(v) for v in cfg.split(","))
+            v = [int(u) for u in cfg.split(",")]
+            no, wi, k2 = v[0], v[1], (v[2] if len(v) > 2 else 0)
             torch.cuda.synchronize()
+            hf.timing_enable(True)
+            hf.timing_read()
             t = time.perf_counter()
-            ids, _ = hf.knn_graph(x, no, wi, args.k, 3)
+            ids, _ = hf.knn_graph(x, no, wi, args.k, 3, k2=k2, sketch_seed=6)
             torch.cuda.synchronize()
-            log("graph sweep orders=%d w=%d: recall %.4f, %.3f s" % (no, wi, recall(ids[rows], gt),
-                                                                    time.perf_counter() - t))
+            el = time.perf_counter() - t
+            st = hf.timing_read()
+            hf.timing_enable(False)
+            log("graph sweep orders=%d w=%d k2=%d: recall %.4f, %.3f s %s" % (
+                no, wi, k2, recall(ids[rows], gt), el,
+                {k_: round(v_[0], 1) for k_, v_ in st.items() if v_[1]}))
     for _ in range(args.warmup):
         hf.knn_graph(x, args.orders, args.window, args.k, 3)
     torch.cuda.synchronize()
@@ -398,7 +405,8 @@ def main():
     ap.add_argument("--h", type=int, default=3)
     ap.add_argument("--orders", type=int, default=264)
     ap.add_argument("--window", type=int, default=128)
-    ap.add_argument("--sweep", default=None, help="extra search configs 'k1,k2,h;k1,k2,h'")
+    ap.add_argument("--sweep", default=None,
+                    help="extra configs: search 'k1,k2,h;...', graph 'orders,w[,k2];...'")
     ap.add_argument("--forms", default="bf16,fp8", help="precision forms measured after the plain search")
     ap.add_argument("--learned", type=int, default=1, help="also train and measure the learned sketch form")
     ap.add_argument("--learned-queries", type=int, default=20000)

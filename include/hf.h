@@ -289,8 +289,9 @@ hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash
  * each launch of the hot kernels (thread-local; off by default).  Stages:
  * 0 query codes, 1 query sketches, 2 descend, 3 hamming, 4 select, 5 rerank,
  * 6 graph sort, 7 graph band, 8 build sort, 9 build trie, 10 build sketch,
- * 11 lowprec score. */
-#define HF_N_STAGES 12
+ * 11 lowprec score, 12 graph hamming band, 13 graph list merge, 14 graph
+ * final cosine top-k. */
+#define HF_N_STAGES 15
 hf_status hf_timing_enable(int32_t on);
 /* Waits for the recorded events, writes the summed milliseconds and launch
  * counts of every stage since the last read (arrays of HF_N_STAGES), clears. */
@@ -302,13 +303,26 @@ const char* hf_timing_stage_name(int32_t stage);
 /* Algorithm 2: for each of n orders (Hilbert sort along seeded curve t),
  * every point gets the points within +-w positions as candidates; the result
  * is, per point, the top-k of the union of its candidates (self excluded) by
- * (cosine similarity, descending; id ascending); with k2 > 0 the candidates
- * are first cut to the k2 with the smallest (Hamming distance, id).
- * ids_dev: N x k int32 original ids (-1 if fewer candidates); scores_dev:
- * N x k FP32 cosines. fp16 data only.  Synchronises. */
+ * (cosine similarity, descending; id ascending).  With k2 > 0 (the
+ * second-stage filtering of Algorithm 2) the union is first cut to the k2
+ * candidates with the smallest (Hamming distance of 512-bit sketches, id):
+ * SRP sketches seeded by sketch_seed, or the learned hash `lhash`
+ * (sketch = HF_SKETCH_LEARNED; the handle must outlive the call).
+ * X_dev: N x d fp16, 16-byte aligned, d a multiple of 8 (HF_ERR_UNSUPPORTED
+ * otherwise).  ids_dev: N x k int32 original ids (-1 if fewer candidates);
+ * scores_dev: N x k FP32 cosines; both caller-owned.  Synchronises.
+ * The sketch stage stages up to 2w keys per position for chunks of positions
+ * whose staging fits HF_GRAPH_STAGE_MIB MiB (environment; default 1024). */
 hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
                        const hf_graph_params* params, int32_t* ids_dev, float* scores_dev,
                        void* stream);
+
+/* hf_knn_graph with k2 > 0 that also writes every point's C2 (the k2
+ * candidates by ascending (Hamming distance, id)): c2_dev N x k2 int32, -1
+ * where fewer than k2 candidates exist.  Same limits and errors. */
+hf_status hf_knn_graph_debug(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
+                             const hf_graph_params* params, int32_t* ids_dev, float* scores_dev,
+                             int32_t* c2_dev, void* stream);
 
 #ifdef __cplusplus
 }

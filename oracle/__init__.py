@@ -60,7 +60,7 @@ def lib():
             "hfo_srp": (None, [P, i32, i64, i32, u64, P]),
             "hfo_search_stage2": (None, [P, i32, i64, i32, P, P, i32, P, P, P, P, i64,
                                          i32, i32, i32, i32, P, P, P, P, P, P]),
-            "hfo_graph_rows": (None, [P, i32, i64, i32, P, i32, i32, P, i64, i32, i32, P, P, P, P]),
+            "hfo_graph_rows": (None, [P, i32, i64, i32, P, i32, i32, P, i64, i32, i32, P, P, P, P, P]),
             "hfo_bf16": (C.c_double, [C.c_double]),
             "hfo_e4m3_decode": (C.c_double, [C.c_uint8]),
             "hfo_e4m3_encode": (C.c_uint8, [C.c_float]),
@@ -316,18 +316,22 @@ def graph_orders(x: np.ndarray, n: int, seed: int, quant_e=None):
     return orders, e
 
 
-def graph_rows(x, orders, w: int, k: int, rows, k2: int = 0, sk=None):
-    """Rows of the Alg. 2 graph: (ids[nrows,k], cos[nrows,k], |C1|[nrows])."""
+def graph_rows(x, orders, w: int, k: int, rows, k2: int = 0, sk=None, with_c2: bool = False):
+    """Rows of the Alg. 2 graph: (ids[nrows,k], cos[nrows,k], |C1|[nrows]) and, with
+    ``with_c2`` (k2 > 0), C2[nrows,k2] in (Hamming, id) order, -1 padded."""
     x = np.ascontiguousarray(x)
     N, d = x.shape
     rows = np.ascontiguousarray(np.asarray(rows, np.int64))
     ids = np.empty((rows.size, k), np.int32)
     sc = np.empty((rows.size, k), np.float64)
     c1n = np.empty(rows.size, np.int32)
+    c2 = np.empty((rows.size, k2), np.int32) if (with_c2 and k2 > 0) else None
     orders = np.ascontiguousarray(orders, np.uint32)
     lib().hfo_graph_rows(_p(x), _dtype_code(x), N, d, _p(orders), orders.shape[0], w, _p(rows),
                          rows.size, k, k2, _p(None if sk is None else np.ascontiguousarray(sk)),
-                         _p(ids), _p(sc), _p(c1n))
+                         _p(ids), _p(sc), _p(c1n), _p(c2))
+    if with_c2:
+        return ids, sc, c1n, c2
     return ids, sc, c1n
 
 

@@ -775,13 +775,15 @@ double hfo_lhash_grad(const void *A, const void *Bm, int32_t dtype, int64_t B, i
 /*           p's rank in order t (window clipped to the array);              */
 /*   k2 > 0: C2(p) = first k2 of C1(p) by (Hamming, id); else C2 = C1;       */
 /*   S(p)  = top-k of C2(p) by (cosine desc, id asc) in FP64.                */
+/* c2_out (nullable, k2 > 0): C2(p) in (Hamming, id) order, -1 padded to k2. */
 /* Pinned: w >= N reduces to the exact brute-force graph (tests).            */
 /* ------------------------------------------------------------------------ */
 static int cmp_key_r(const void *a, const void *b) { return cmp_ham_pos(a, b); }
 
 void hfo_graph_rows(const void *X, int32_t dtype, int64_t N, int32_t d, const uint32_t *orders,
                     int32_t n, int32_t w, const int64_t *rows, int64_t nrows, int32_t k, int32_t k2,
-                    const uint64_t *sk, int32_t *out_ids, double *out_scores, int32_t *c1n) {
+                    const uint64_t *sk, int32_t *out_ids, double *out_scores, int32_t *c1n,
+                    int32_t *c2_out) {
   uint32_t *rank = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N * n));
   for (int32_t t = 0; t < n; ++t)
     for (int64_t i = 0; i < N; ++i) rank[(int64_t)t * N + orders[(int64_t)t * N + i]] = (uint32_t)i;
@@ -820,6 +822,8 @@ void hfo_graph_rows(const void *X, int32_t dtype, int64_t N, int32_t d, const ui
       if (k2 > 0) {
         qsort(buf, (size_t)n1, sizeof(cand), cmp_key_r);
         if (n2 > k2) n2 = k2;
+        if (c2_out)
+          for (int32_t i = 0; i < k2; ++i) c2_out[ri * k2 + i] = i < n2 ? (int32_t)buf[i].r : -1;
       }
       for (int64_t i = 0; i < n2; ++i) {
         int64_t c = buf[i].r;

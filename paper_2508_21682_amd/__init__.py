@@ -30,8 +30,9 @@ EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_qu
            "hf_forest_sketches", "hf_search", "hf_search_debug", "hf_knn_graph",
            "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name", "hf_forest_add_precision",
            "hf_search_lowprec_debug", "hf_audit_scores", "hf_lhash_create", "hf_lhash_free", "hf_lhash_get",
-           "hf_lhash_encode", "hf_lhash_grad", "hf_lhash_train", "hf_forest_set_sketch"]
-N_STAGES = 12
+           "hf_lhash_encode", "hf_lhash_grad", "hf_lhash_train", "hf_forest_set_sketch",
+           "hf_knn_graph_debug"]
+N_STAGES = 15
 
 
 class HFError(RuntimeError):
@@ -134,6 +135,7 @@ def lib():
             "hf_lhash_grad": (C.c_int, [P, P, P, C.c_int, i64, i32, P, P, P, P, P, P, P]),
             "hf_lhash_train": (C.c_int, [P, P, P, C.c_int, i64, i32, P, P, P]),
             "hf_forest_set_sketch": (C.c_int, [P, C.c_int, P, P]),
+            "hf_knn_graph_debug": (C.c_int, [P, C.c_int, i64, i32, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -418,15 +420,36 @@ class LHash:
 
 
 # ---------------------------------------------------------------- graph
+def _graph_params(n_orders, window, k, seed, k2, sketch, sketch_seed, lhash, quant_exp):
+    kind = {"srp": HF_SKETCH_SRP, "learned": HF_SKETCH_LEARNED}[sketch]
+    return GraphParams(C.sizeof(GraphParams), n_orders, window, k, k2,
+                       HF_QUANT_AUTO if quant_exp is None else quant_exp, kind, seed, sketch_seed,
+                       None if lhash is None else lhash._h.value)
+
+
 def knn_graph(x, n_orders: int, window: int, k: int, seed: int, k2: int = 0, sketch_seed: int = 0,
-              quant_exp: int | None = None):
+              quant_exp: int | None = None, sketch: str = "srp", lhash=None):
+    """Algorithm 2 graph: (ids N x k int32, cosines N x k float32); k2 > 0 adds the sketch stage."""
     x = _dev(x)
     N, d = x.shape
     t = _torch()
     ids = _empty((N, k), t.int32, x)
     sc = _empty((N, k), t.float32, x)
-    p = GraphParams(C.sizeof(GraphParams), n_orders, window, k, k2,
-                    HF_QUANT_AUTO if quant_exp is None else quant_exp, HF_SKETCH_SRP, seed, sketch_seed,
-                    None)
+    p = _graph_params(n_orders, window, k, seed, k2, sketch, sketch_seed, lhash, quant_exp)
     _check(lib().hf_knn_graph(_ptr(x), _dtype(x), N, d, C.byref(p), _ptr(ids), _ptr(sc), _stream()))
     return ids, sc
+
+
+def knn_graph_debug(x, n_orders: int, window: int, k: int, seed: int, k2: int, sketch_seed: int = 0,
+                    quant_exp: int | None = None, sketch: str = "srp", lhash=None):
+    """knn_graph with the sketch stage, also returning every point's C2 (N x k2 ids, -1 padded)."""
+    x = _dev(x)
+    N, d = x.shape
+    t = _torch()
+    ids = _empty((N, k), t.int32, x)
+    sc = _empty((N, k), t.float32, x)
+    c2 = _empty((N, k2), t.int32, x)
+    p = _graph_params(n_orders, window, k, seed, k2, sketch, sketch_seed, lhash, quant_exp)
+    _check(lib().hf_knn_graph_debug(_ptr(x), _dtype(x), N, d, C.byref(p), _ptr(ids), _ptr(sc), _ptr(c2),
+                                    _stream()))
+    return ids, sc, c2

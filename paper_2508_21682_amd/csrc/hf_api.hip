@@ -33,7 +33,8 @@ thread_local std::vector<TimedSpan> t_spans;
 thread_local std::vector<hipEvent_t> t_open(ST_COUNT, nullptr);
 const char* kStageNames[ST_COUNT] = {"query_codes", "query_sketch", "descend", "hamming", "select",
                                      "rerank", "graph_sort", "graph_band", "build_sort", "build_trie",
-                                     "build_sketch", "lowprec_score"};
+                                     "build_sketch", "lowprec_score", "graph_hamming", "graph_merge",
+                                     "graph_final"};
 }  // namespace
 
 bool timing_on() { return t_on; }
@@ -85,7 +86,7 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
                         int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
                         hipStream_t s);
 hf_status graph_launch(const void* X, hf_dtype dt, int64_t N, int d, const hf_graph_params& p,
-                       int e, int32_t* ids, float* scores, hipStream_t s);
+                       int e, int32_t* ids, float* scores, int32_t* c2_ids, hipStream_t s);
 
 namespace {
 
@@ -558,8 +559,8 @@ hf_status hf_audit_scores(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   return audit_launch(X_dev, dtype, d, Q_dev, nq, ids_dev, k, out_dev, (hipStream_t)stream);
 }
 
-hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const hf_graph_params* p,
-                       int32_t* ids_dev, float* scores_dev, void* stream) {
+static hf_status knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const hf_graph_params* p,
+                           int32_t* ids_dev, float* scores_dev, int32_t* c2_dev, void* stream) {
   clear_error();
   HF_ARG(X_dev && p && ids_dev && scores_dev, "null pointer");
   HF_ARG(p->struct_size == sizeof(hf_graph_params), "struct_size mismatch");
@@ -571,13 +572,15 @@ hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, 
   HF_ARG(p->k >= 1 && p->k <= 32, "k must be in [1, 32]");
   HF_ARG(p->k2 == 0 || (p->k2 >= p->k && p->k2 <= 256), "k2 must be 0 or in [k, 256]");
   HF_ARG(p->quant_exp == HF_QUANT_AUTO || (p->quant_exp >= -8 && p->quant_exp <= 24), "bad quant_exp");
+  HF_ARG(p->k2 == 0 || p->sketch == HF_SKETCH_SRP || p->sketch == HF_SKETCH_LEARNED, "bad sketch kind");
+  HF_ARG(((uintptr_t)X_dev & 15) == 0, "X_dev must be 16-byte aligned");
   if (dtype != HF_F16 || d % 8 != 0) {
     set_error("the graph kernels take fp16 rows with d a multiple of 8");
     return HF_ERR_UNSUPPORTED;
   }
-  if (p->k2 > 0 && p->sketch != HF_SKETCH_SRP) {
-    set_error("only SRP sketches are supported in the graph prefilter");
-    return HF_ERR_UNSUPPORTED;
+  if (p->k2 > 0 && p->sketch == HF_SKETCH_LEARNED) {
+    HF_ARG(p->lhash != nullptr, "learned sketches need a hash");
+    HF_ARG(lhash_dim(p->lhash) == d, "the hash's input size differs from d");
   }
   hipStream_t s = (hipStream_t)stream;
   int e;
@@ -585,7 +588,19 @@ hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, 
     Workspace ws(s);
     HF_TRY(data_exp(X_dev, dtype, N * d, p->quant_exp, &e, ws));
   }
-  return graph_launch(X_dev, dtype, N, d, *p, e, ids_dev, scores_dev, s);
+  return graph_launch(X_dev, dtype, N, d, *p, e, ids_dev, scores_dev, c2_dev, s);
+}
+
+hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const hf_graph_params* p,
+                       int32_t* ids_dev, float* scores_dev, void* stream) {
+  return knn_graph(X_dev, dtype, N, d, p, ids_dev, scores_dev, nullptr, stream);
+}
+
+hf_status hf_knn_graph_debug(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d, const hf_graph_params* p,
+                             int32_t* ids_dev, float* scores_dev, int32_t* c2_dev, void* stream) {
+  clear_error();
+  HF_ARG(p && p->k2 > 0 && c2_dev, "the debug graph needs k2 > 0 and a C2 buffer");
+  return knn_graph(X_dev, dtype, N, d, p, ids_dev, scores_dev, c2_dev, stream);
 }
 
 }  // extern "C"

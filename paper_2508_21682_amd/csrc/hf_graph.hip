@@ -12,6 +12,7 @@
 // skipped; one that was evicted earlier is evicted again (its score is
 // fixed), so the list stays the top-k of the union of all windows seen.
 #include <math.h>
+#include <stdlib.h>
 
 #include "hf_internal.h"
 
@@ -106,14 +107,6 @@ __device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t
   if (r < 0 || k0 >= d) return (half8)(0);
   uint4 raw = *(const uint4*)(X + r * d + k0);
   return __builtin_bit_cast(half8, raw);
-}
-
-// LDS written and read by the same wavefront only: order the accesses
-// without a block barrier.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int KMAX, int KS>
@@ -231,13 +224,75 @@ hf_status launch_band(int ks, const __half* X, int64_t N, int d, const uint32_t*
 
 }  // namespace
 
-hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_graph_params& p, int e,
-                       int32_t* ids, float* scores, hipStream_t s) {
-  (void)dt;
-  if (p.k2 != 0) {
-    set_error("the sketch prefilter of the graph is not built");
-    return HF_ERR_UNSUPPORTED;
+// Algorithm 2 with the sketch stage: per order a Hilbert sort, the Hamming
+// band and the list merge; after the last order the cosine top-k of every
+// point's k2 list.
+static hf_status graph_prefilter(const void* X, int64_t N, int d, const hf_graph_params& p, int e,
+                                 int32_t* ids, float* scores, int32_t* c2_ids, hipStream_t s) {
+  Workspace ws(s);
+  const int w = (int)p.window, k2 = (int)p.k2;
+  uint64_t* sk;
+  HF_TRY(ws.alloc(&sk, (size_t)N * 8));
+  if (p.sketch == HF_SKETCH_LEARNED) {
+    HF_TRY(lhash_encode_dev(p.lhash, X, HF_F16, N, sk, s));
+  } else {
+    HF_TRY(srp_sketch(X, HF_F16, N, d, e, p.sketch_seed, sk, ws));
   }
+  uint8_t* codes;
+  float* nrm;
+  uint32_t* order;
+  uint64_t* lists;
+  HF_TRY(ws.alloc(&codes, (size_t)(N * d)));
+  HF_TRY(ws.alloc(&nrm, (size_t)N));
+  HF_TRY(ws.alloc(&order, (size_t)N));
+  HF_TRY(ws.alloc(&lists, (size_t)N * k2));
+  // staging of one chunk of positions: 2w keys each, HF_GRAPH_STAGE_MIB
+  // (default 1024) MiB at most
+  int64_t stage_mib = 1024;
+  if (const char* v = getenv("HF_GRAPH_STAGE_MIB")) stage_mib = std::max<int64_t>(1, atoll(v));
+  int64_t chunk = (stage_mib << 17) / (2 * w);
+  chunk = std::max<int64_t>(256, chunk / 256 * 256);
+  chunk = std::min<int64_t>(chunk, N);
+  uint64_t* stage;
+  uint32_t* cnt;
+  HF_TRY(ws.alloc(&stage, (size_t)(2 * w) * chunk));
+  HF_TRY(ws.alloc(&cnt, (size_t)chunk));
+  HF_TRY(quantize(X, HF_F16, N * d, e, codes, s));
+  uint32_t* msb = nullptr;
+  if (msb_words(d) > 0) {
+    HF_TRY(ws.alloc(&msb, (size_t)(N * msb_words(d))));
+    HF_TRY(msb_plane(codes, N, d, msb, s));
+  }
+  k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>((const __half*)X, N, d, nrm);
+  HF_LAUNCH_CHECK();
+  HF_TRY(gpf_init_lists(lists, N * k2, s));
+  const int T = (int)p.n_orders;
+  std::vector<int32_t> perm((size_t)T * d);
+  std::vector<uint8_t> refl((size_t)T * d);
+  make_curves(p.seed, T, d, perm.data(), refl.data());
+  int32_t* dperm;
+  uint8_t* drefl;
+  HF_TRY(ws.alloc(&dperm, (size_t)T * d));
+  HF_TRY(ws.alloc(&drefl, (size_t)T * d));
+  HIP_TRY(hipMemcpyAsync(dperm, perm.data(), 4 * (size_t)T * d, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(drefl, refl.data(), (size_t)T * d, hipMemcpyHostToDevice, s));
+  for (int t = 0; t < T; ++t) {
+    Workspace wt(s);
+    {
+      StageTimer tm(ST_GSORT, s);
+      HF_TRY(hilbert_sort_dev(codes, msb, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
+    }
+    HF_TRY(gpf_order(sk, order, N, w, k2, lists, chunk, stage, cnt, s));
+  }
+  HF_TRY(gpf_final(X, nrm, N, d, lists, k2, (int)p.k, ids, scores, c2_ids, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return HF_OK;
+}
+
+hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_graph_params& p, int e,
+                       int32_t* ids, float* scores, int32_t* c2_ids, hipStream_t s) {
+  (void)dt;
+  if (p.k2 != 0) return graph_prefilter(Xv, N, d, p, e, ids, scores, c2_ids, s);
   const __half* X = (const __half*)Xv;
   int ks = (d + 31) / 32;
   if (ks > 16) ks = ks <= 20 ? 20 : (ks <= 24 ? 24 : (ks <= 32 ? 32 : 0));

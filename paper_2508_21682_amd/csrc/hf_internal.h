@@ -154,6 +154,14 @@ __device__ __forceinline__ uint32_t float_to_ordered(float f) {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// LDS written and read by the same wavefront only: order the accesses
+// without a block barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 inline int bits_for(uint64_t max_value) {
   int b = 0;
   while (b < 64 && (max_value >> b) != 0) ++b;
@@ -197,7 +205,7 @@ hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64
                      uint64_t* out, Workspace& ws);
 // stage timing (hf_api.hip): events around a launch when timing is on
 enum Stage { ST_QCODES = 0, ST_QSKETCH, ST_DESCEND, ST_HAM, ST_SELECT, ST_RERANK, ST_GSORT, ST_GBAND,
-             ST_BSORT, ST_BTRIE, ST_BSKETCH, ST_LOWPREC, ST_COUNT };
+             ST_BSORT, ST_BTRIE, ST_BSKETCH, ST_LOWPREC, ST_GHAM, ST_GMERGE, ST_GFINAL, ST_COUNT };
 bool timing_on();
 void timing_mark(int stage, bool begin, hipStream_t s);
 struct StageTimer {
@@ -214,6 +222,16 @@ hf_status rerank_lp_launch(const hf_forest* f, hf_precision prec, const void* Qb
                            int32_t* enb, hipStream_t s);
 hf_status audit_launch(const void* X, hf_dtype dt, int d, const void* Q, int64_t nq, const int32_t* ids,
                        int k, double* out, hipStream_t s);
+// hf_gprefilter.hip: sketch prefilter of the graph.  lists: N x k2 keys
+// (Hamming << 32 | id), ascending, empty slots all-ones.
+constexpr int GRAPH_K2_MAX = 256;
+hf_status gpf_init_lists(uint64_t* lists, int64_t n, hipStream_t s);
+// One order: stage holds 2w x chunk keys, cnt chunk counters.
+hf_status gpf_order(const uint64_t* sk, const uint32_t* order, int64_t N, int w, int k2, uint64_t* lists,
+                    int64_t chunk, uint64_t* stage, uint32_t* cnt, hipStream_t s);
+// Final cosine top-k of every list; c2_ids (nullable) receives the listed ids (-1 if empty).
+hf_status gpf_final(const void* X, const float* nrm, int64_t N, int d, const uint64_t* lists, int k2, int k,
+                    int32_t* ids, float* sc, int32_t* c2_ids, hipStream_t s);
 // hf_lhash.hip
 hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_t N, uint64_t* sk, hipStream_t s);
 int lhash_dim(const hf_lhash* L);

@@ -441,7 +441,7 @@ hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_
   return HF_OK;
 }
 
-int lhash_dim(const hf_lhash* L) { return L ? L->d : 0; }
+int lhash_dim(const hf_lhash* L) { return (L && L->magic == HF_LHASH_MAGIC) ? L->d : 0; }
 
 }  // namespace hf
 

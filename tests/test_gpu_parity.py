@@ -249,6 +249,91 @@ def test_graph_parity_ragged(hf, orc):
     _graph_case(hf, orc, x, n=2, w=49, k=20, seed=5, rows=np.arange(100))
 
 
+def _graph_prefilter_case(hf, orc, x, n, w, k, k2, seed, sk_seed, rows):
+    """Sketch stage of Alg. 2: C2 lists bit-exact, results as in the plain form."""
+    orders, e = orc.graph_orders(x, n, seed)
+    sk = orc.srp(x, e, sk_seed)
+    oi, os_, _, oc2 = orc.graph_rows(x, orders, w, k, rows, k2=k2, sk=sk, with_c2=True)
+    gi, gs, gc2 = hf.knn_graph_debug(dev(x), n, w, k, seed, k2, sketch_seed=sk_seed)
+    assert (gc2.cpu().numpy()[rows] == oc2).all()
+    gi2, gs2 = hf.knn_graph(dev(x), n, w, k, seed, k2=k2, sketch_seed=sk_seed)
+    assert (gi2.cpu().numpy() == gi.cpu().numpy()).all() and (gs2.cpu().numpy() == gs.cpu().numpy()).all()
+    gi, gs = gi.cpu().numpy()[rows], gs.cpu().numpy()[rows]
+    fin = np.isfinite(os_)
+    assert (np.isfinite(gs) == fin).all() and ((gi == -1) == ~fin).all()
+    assert np.abs(gs[fin] - os_[fin]).max() <= TOL
+    X = x.astype(np.float64)
+    nrm = np.linalg.norm(X, axis=1)
+    for i, p in enumerate(rows):
+        kth = os_[i][fin[i]][-1]
+        for c in set(gi[i].tolist()) ^ set(oi[i].tolist()):
+            assert c >= 0
+            assert abs(X[p] @ X[c] / (nrm[p] * nrm[c]) - kth) <= TOL
+
+
+def test_graph_prefilter_parity_d384(hf, orc):
+    x = datagen.mixture(20000, 384, 32, 0.05, 74, dtype=np.float16)
+    rows = np.random.default_rng(3).choice(20000, 1500, replace=False)
+    _graph_prefilter_case(hf, orc, x, n=4, w=32, k=15, k2=50, seed=3, sk_seed=9, rows=rows)
+
+
+def test_graph_prefilter_wide_window(hf, orc):
+    """w = 130: the sketch ring of the band kernel cycles through five blocks."""
+    x = datagen.mixture(5000, 64, 8, 0.1, 75, dtype=np.float16)
+    _graph_prefilter_case(hf, orc, x, n=2, w=130, k=10, k2=100, seed=4, sk_seed=10, rows=np.arange(0, 5000, 3))
+
+
+def test_graph_prefilter_ragged(hf, orc):
+    # k2 == k; a ragged N and d
+    x = datagen.mixture(333, 40, 4, 0.1, 76, dtype=np.float16)
+    _graph_prefilter_case(hf, orc, x, n=3, w=21, k=7, k2=7, seed=5, sk_seed=11, rows=np.arange(333))
+    # lists never fill (k2 above every union): C2 = C1, padded
+    x = datagen.mixture(100, 16, 2, 0.2, 77, dtype=np.float16)
+    _graph_prefilter_case(hf, orc, x, n=2, w=49, k=20, k2=256, seed=6, sk_seed=12, rows=np.arange(100))
+    # fewer candidates than k: -1 / -inf tails
+    x = datagen.mixture(40, 8, 2, 0.2, 78, dtype=np.float16)
+    _graph_prefilter_case(hf, orc, x, n=1, w=2, k=6, k2=6, seed=7, sk_seed=13, rows=np.arange(40))
+
+
+def test_graph_prefilter_chunked_staging(hf, orc, monkeypatch):
+    """Positions staged in several chunks per order (1 MiB of staging)."""
+    monkeypatch.setenv("HF_GRAPH_STAGE_MIB", "1")
+    x = datagen.mixture(9000, 32, 8, 0.1, 79, dtype=np.float16)
+    _graph_prefilter_case(hf, orc, x, n=3, w=40, k=10, k2=30, seed=8, sk_seed=14, rows=np.arange(0, 9000, 4))
+
+
+def test_graph_prefilter_learned_sketch(hf, orc):
+    """With learned sketches C2 is the k2 smallest (Hamming, id) of the window
+    union under the library's own codes of the points (its encoder is checked
+    against the oracle separately), and the result is the cosine top-k of C2."""
+    W = _net(97, d=64, hid=256)
+    x = datagen.mixture(3000, 64, 8, 0.1, 80, dtype=np.float16)
+    L = hf.LHash(*W)
+    sk = L.encode(dev(x)).cpu().numpy().view(np.uint64)
+    n, w, k, k2 = 3, 24, 8, 30
+    gi, gs, gc2 = hf.knn_graph_debug(dev(x), n, w, k, 5, k2, sketch="learned", lhash=L)
+    gi, gs, gc2 = gi.cpu().numpy(), gs.cpu().numpy(), gc2.cpu().numpy()
+    orders, _ = orc.graph_orders(x, n, 5)
+    rank = np.empty((n, x.shape[0]), np.int64)
+    for t in range(n):
+        rank[t, orders[t]] = np.arange(x.shape[0])
+    X = x.astype(np.float64)
+    nrm = np.linalg.norm(X, axis=1)
+    for p in range(0, x.shape[0], 7):
+        C1 = set()
+        for t in range(n):
+            i = rank[t, p]
+            C1 |= set(orders[t][max(0, i - w):i + w + 1].tolist())
+        C1.discard(p)
+        C1 = np.array(sorted(C1), np.int64)
+        hm = np.bitwise_count(sk[C1] ^ sk[p][None, :]).sum(1)
+        want = C1[np.lexsort((C1, hm))][:k2]
+        assert gc2[p].tolist() == want.tolist()
+        cos = X[want] @ X[p] / (nrm[want] * nrm[p])
+        assert np.abs(np.sort(cos)[::-1][:k] - gs[p]).max() <= TOL
+    L.free()
+
+
 # ------------------------------------------------------------------ precision form
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_precision_form_parity(hf, orc, prec):

@@ -392,13 +392,16 @@ def test_graph_window_sets_tiny(orc):
         assert ids[ri].tolist() == sorted(C1, key=lambda c: (-cos[c], c))[:k]
 
 
-def test_graph_prefilter_by_hamming(orc):
+@pytest.mark.parametrize("w,k,k2", [(6, 4, 9), (3, 4, 40)])
+def test_graph_prefilter_by_hamming(orc, w, k, k2):
+    """C2 = the k2 smallest (Hamming, id) of the window union, -1 padded when
+    the union is smaller; the result is the cosine top-k of C2 (Python sets,
+    popcounts of Python integers)."""
     x = datagen.mixture(150, 16, 3, 0.2, 12, dtype=np.float16)
     orders, e = orc.graph_orders(x, 2, 5)
     sk = orc.srp(x, e, 13)
     rows = np.arange(0, 150, 5)
-    w, k, k2 = 6, 4, 9
-    ids, sc, c1n = orc.graph_rows(x, orders, w, k, rows, k2=k2, sk=sk)
+    ids, sc, c1n, c2 = orc.graph_rows(x, orders, w, k, rows, k2=k2, sk=sk, with_c2=True)
     X = x.astype(np.float64)
     for ri, p in enumerate(rows):
         C1 = set()
@@ -406,10 +409,12 @@ def test_graph_prefilter_by_hamming(orc):
             i = int(np.where(orders[t] == p)[0][0])
             C1 |= set(int(v) for v in orders[t][max(0, i - w):i + w + 1])
         C1.discard(int(p))
-        hm = {c: int(orc.hamming(sk[p], sk[c])) for c in C1}
+        hm = {c: sum(bin(int(a) ^ int(b)).count("1") for a, b in zip(sk[p], sk[c])) for c in C1}
         C2 = sorted(C1, key=lambda c: (hm[c], c))[:k2]
+        assert c2[ri].tolist() == C2 + [-1] * (k2 - len(C2))
         cos = {c: X[p] @ X[c] / (np.linalg.norm(X[p]) * np.linalg.norm(X[c])) for c in C2}
-        assert ids[ri].tolist() == sorted(C2, key=lambda c: (-cos[c], c))[:k]
+        want = sorted(C2, key=lambda c: (-cos[c], c))[:k]
+        assert ids[ri].tolist() == want + [-1] * (k - len(want))
 
 
 # ----------------------------------------------------------------- precision emulation

@@ -117,6 +117,7 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   __shared__ float band[4][16][17];
   __shared__ int32_t colid[4][16];
   __shared__ float coln[4][16];
+  __shared__ uint32_t pass[4][16];  // per row: byte g holds the pass bits of columns 4g..4g+3
   const int wv = threadIdx.x / 64, l = __lane_id();
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
   if (r0 >= N) return;  // no block barriers below: waves are independent
@@ -141,6 +142,10 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
     }
   }
   L.refresh(k);
+  // row threshold in dot-product units, for the screening test of all lanes
+  float wsn = L.ws * own_n;
+  int open = L.wi < 0;
+  const bool row_ok = arow >= 0;
   const int wr = (w + 15) / 16;
   const int nblk = 1 + 2 * wr;
   half8 B[KS];
@@ -176,17 +181,46 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
       cn = brow >= 0 ? ns[brow] : 1.f;
     }
     wave_lds_sync();
-    if (owner) {
+    // Screening by all 64 lanes: lane (ri, kg) tests row ri against columns
+    // 4kg..4kg+3.  A column fails only if its dot product is below the row's
+    // k-th cosine times the two norms by a relative 2^-20, far beyond the
+    // rounding of either side, so it cannot beat the k-th entry exactly.
+    {
+      const float t_ws = __shfl(wsn, ri);
+      const int t_open = __shfl(open, ri);
+      const int off = (int)(c0 - (r0 + ri));  // column j is at offset j + off from the row
+      uint32_t bits = 0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = 4 * kg + jj;
+        const int delta = j + off;
         const int64_t cp = c0 + j;
-        const int64_t delta = cp - own;
-        if (delta == 0 || delta > w || -delta > w || cp < 0 || cp >= N) continue;
-        const float cs = band[wv][l][j] / (own_n * coln[wv][j]);
-        const int32_t c = colid[wv][j];
-        if (!(L.wi < 0 || better(cs, c, L.ws, L.wi))) continue;
-        L.insert(k, cs, c);
+        const float b = band[wv][ri][j];
+        const float t = t_ws * coln[wv][j];
+        const bool ok = row_ok && delta != 0 && delta <= w && -delta <= w && cp >= 0 && cp < N &&
+                        (t_open || b >= t - fabsf(t) * 0x1p-20f);
+        bits |= (uint32_t)ok << jj;
       }
+      ((uint8_t*)&pass[wv][ri])[kg] = (uint8_t)bits;
+    }
+    wave_lds_sync();
+    uint32_t m = 0;
+    if (owner) {
+      const uint32_t x = pass[wv][l];
+      m = (x & 0xFu) | ((x >> 4) & 0xF0u) | ((x >> 8) & 0xF00u) | ((x >> 12) & 0xF000u);
+    }
+    if (__ballot(m != 0)) {
+      while (__ballot(m != 0)) {
+        if (m) {
+          const int j = __builtin_ctz(m);
+          m &= m - 1;
+          const float cs = band[wv][l][j] / (own_n * coln[wv][j]);
+          const int32_t c = colid[wv][j];
+          if (L.wi < 0 || better(cs, c, L.ws, L.wi)) L.insert(k, cs, c);
+        }
+      }
+      wsn = L.ws * own_n;
+      open = L.wi < 0;
     }
     wave_lds_sync();
   }

@@ -1,16 +1,18 @@
 // k-NN graph from windows along several Hilbert orders (Section 4.1,
 // Algorithm 2).  Per order: Hilbert sort of all points, then a band kernel.
 //
-// Band kernel: a wavefront owns 16 consecutive positions of the order.  Their
-// rows (fp16, gathered through the order) stay in registers as the A operand
-// of v_mfma_f32_16x16x32_f16; the rows of each 16-position block within +-w
-// stream through as the B operand, so every MFMA tile is a 16x16 block of dot
-// products along the band.  Cosines (FP32 accumulate, FP32 norms) of the
-// pairs with 0 < |i-j| <= w are merged by the row's owner lane into that
-// point's top-k list (cosine desc, id asc), held in registers while the wave
-// runs and in HBM between orders.  A candidate already in the list is
-// skipped; one that was evicted earlier is evicted again (its score is
-// fixed), so the list stays the top-k of the union of all windows seen.
+// Band kernel: a workgroup owns 64 consecutive positions of the order, a
+// wavefront 16 of them.  Their rows (fp16, gathered through the order) stay in
+// registers as the A operand of v_mfma_f32_16x16x32_f16; the rows of each
+// 16-position block within +-w stream through a shared LDS tile as the B
+// operand, so every MFMA tile is a 16x16 block of dot products along the
+// band.  All 64 lanes screen the tile's pairs against each row's current k-th
+// entry; cosines (FP32 accumulate, FP32 norms) of the survivors with
+// 0 < |i-j| <= w are merged by the row's owner lane into that point's top-k
+// list (cosine desc, id asc), held in registers while the wave runs and in
+// HBM between orders.  A candidate already in the list is skipped; one that
+// was evicted earlier is evicted again (its score is fixed), so the list
+// stays the top-k of the union of all windows seen.
 #include <math.h>
 #include <stdlib.h>
 
@@ -109,18 +111,28 @@ __device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t
   return __builtin_bit_cast(half8, raw);
 }
 
+// A workgroup (four wavefronts) owns 64 consecutive positions; wavefront v
+// owns rows R0+16v .. +15.  Column blocks of 16 positions stream through a
+// double-buffered LDS tile shared by the four wavefronts (loaded once, one
+// step ahead, 16-byte coalesced); wavefront v uses blocks v .. v+2*wr of the
+// workgroup's 4+2*wr.  Rows are padded by 16 bytes in LDS so the 16 lanes
+// reading one column fragment hit distinct banks.
 template <int KMAX, int KS>
 __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int64_t N, int d,
                                               const uint32_t* __restrict__ order,
                                               const float* __restrict__ ns, int w, int k,
                                               int32_t* __restrict__ gids, float* __restrict__ gsc) {
+  constexpr int RS = KS * 32 + 8;  // LDS row stride (halves)
+  constexpr int CPR = KS * 4;      // 16-byte chunks per tile row
+  constexpr int CH = (16 * CPR + 255) / 256;  // chunks per thread per tile
+  __shared__ __attribute__((aligned(16))) _Float16 tile[2][16 * RS];
+  __shared__ int32_t tcid[2][16];
+  __shared__ float tnrm[2][16];
   __shared__ float band[4][16][17];
-  __shared__ int32_t colid[4][16];
-  __shared__ float coln[4][16];
   __shared__ uint32_t pass[4][16];  // per row: byte g holds the pass bits of columns 4g..4g+3
   const int wv = threadIdx.x / 64, l = __lane_id();
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 16;
-  if (r0 >= N) return;  // no block barriers below: waves are independent
+  const int64_t R0 = (int64_t)blockIdx.x * 64;
+  const int64_t r0 = R0 + 16 * wv;
   const int ri = l % 16, kg = l / 16;
   const int64_t arow = r0 + ri < N ? r0 + ri : -1;
   half8 A[KS];
@@ -147,82 +159,106 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   int open = L.wi < 0;
   const bool row_ok = arow >= 0;
   const int wr = (w + 15) / 16;
-  const int nblk = 1 + 2 * wr;
-  half8 B[KS];
-  int32_t cid;
-  float cn;
-  {
-    const int64_t cpos = r0 - 16 * (int64_t)wr + ri;
-    const int64_t brow = (cpos >= 0 && cpos < N) ? cpos : -1;
+  const int nsteps = 4 + 2 * wr;
+  const int64_t C0 = R0 - 16 * (int64_t)wr;  // first column of block 0
+  // cooperative tile load: chunk x of the tile is row x / CPR, halves 8*(x % CPR)
+  uint4 stg[CH];
+  int32_t scid = -1;
+  float snrm = 1.f;
+  auto fetch = [&](int q) {
+    const int64_t cb0 = C0 + 16 * (int64_t)q;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) B[s] = load_row8(Xs, brow, d, 32 * s + 8 * kg);
-    cid = brow >= 0 ? (int32_t)order[brow] : -1;
-    cn = brow >= 0 ? ns[brow] : 1.f;
-  }
-  for (int cb = 0; cb < nblk; ++cb) {
-    const int64_t c0 = r0 + 16 * (int64_t)(cb - wr);
-    float4v acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B[s], acc, 0, 0, 0);
-    // D layout: lane l holds rows 4*(l/16)+r, column l%16
-#pragma unroll
-    for (int r = 0; r < 4; ++r) band[wv][4 * kg + r][ri] = acc[r];
-    if (kg == 0) {
-      colid[wv][ri] = cid;
-      coln[wv][ri] = cn;
+    for (int i = 0; i < CH; ++i) {
+      const int x = threadIdx.x + 256 * i;
+      const int rr = x / CPR, k0 = 8 * (x % CPR);
+      const int64_t row = cb0 + rr;
+      stg[i] = make_uint4(0, 0, 0, 0);
+      if (x < 16 * CPR && row >= 0 && row < N && k0 < d) stg[i] = *(const uint4*)(Xs + row * d + k0);
     }
-    // prefetch the next column block while this one is merged
-    if (cb + 1 < nblk) {
-      const int64_t cpos = c0 + 16 + ri;
-      const int64_t brow = (cpos >= 0 && cpos < N) ? cpos : -1;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) B[s] = load_row8(Xs, brow, d, 32 * s + 8 * kg);
-      cid = brow >= 0 ? (int32_t)order[brow] : -1;
-      cn = brow >= 0 ? ns[brow] : 1.f;
-    }
-    wave_lds_sync();
-    // Screening by all 64 lanes: lane (ri, kg) tests row ri against columns
-    // 4kg..4kg+3.  A column fails only if its dot product is below the row's
-    // k-th cosine times the two norms by a relative 2^-20, far beyond the
-    // rounding of either side, so it cannot beat the k-th entry exactly.
-    {
-      const float t_ws = __shfl(wsn, ri);
-      const int t_open = __shfl(open, ri);
-      const int off = (int)(c0 - (r0 + ri));  // column j is at offset j + off from the row
-      uint32_t bits = 0;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int j = 4 * kg + jj;
-        const int delta = j + off;
-        const int64_t cp = c0 + j;
-        const float b = band[wv][ri][j];
-        const float t = t_ws * coln[wv][j];
-        const bool ok = row_ok && delta != 0 && delta <= w && -delta <= w && cp >= 0 && cp < N &&
-                        (t_open || b >= t - fabsf(t) * 0x1p-20f);
-        bits |= (uint32_t)ok << jj;
+    scid = -1;
+    snrm = 1.f;
+    if (threadIdx.x < 16) {
+      const int64_t row = cb0 + threadIdx.x;
+      if (row >= 0 && row < N) {
+        scid = (int32_t)order[row];
+        snrm = ns[row];
       }
-      ((uint8_t*)&pass[wv][ri])[kg] = (uint8_t)bits;
     }
-    wave_lds_sync();
-    uint32_t m = 0;
-    if (owner) {
-      const uint32_t x = pass[wv][l];
-      m = (x & 0xFu) | ((x >> 4) & 0xF0u) | ((x >> 8) & 0xF00u) | ((x >> 12) & 0xF000u);
+  };
+  auto store = [&](int slot) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int x = threadIdx.x + 256 * i;
+      if (x < 16 * CPR) *(uint4*)(&tile[slot][(x / CPR) * RS + 8 * (x % CPR)]) = stg[i];
     }
-    if (__ballot(m != 0)) {
-      while (__ballot(m != 0)) {
-        if (m) {
-          const int j = __builtin_ctz(m);
-          m &= m - 1;
-          const float cs = band[wv][l][j] / (own_n * coln[wv][j]);
-          const int32_t c = colid[wv][j];
-          if (L.wi < 0 || better(cs, c, L.ws, L.wi)) L.insert(k, cs, c);
+    if (threadIdx.x < 16) {
+      tcid[slot][threadIdx.x] = scid;
+      tnrm[slot][threadIdx.x] = snrm;
+    }
+  };
+  fetch(0);
+  store(0);
+  for (int q = 0; q < nsteps; ++q) {
+    __syncthreads();  // tile q is in slot q & 1; slot (q + 1) & 1 is free
+    if (q + 1 < nsteps) fetch(q + 1);
+    const int cb = q - wv;
+    if (cb >= 0 && cb <= 2 * wr && r0 < N) {
+      const int slot = q & 1;
+      const int64_t c0 = C0 + 16 * (int64_t)q;
+      float4v acc = {0.f, 0.f, 0.f, 0.f};
+      const _Float16* bt = &tile[slot][ri * RS + 8 * kg];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const half8 B = *(const half8*)(bt + 32 * s);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B, acc, 0, 0, 0);
+      }
+      // D layout: lane l holds rows 4*(l/16)+r, column l%16
+#pragma unroll
+      for (int r = 0; r < 4; ++r) band[wv][4 * kg + r][ri] = acc[r];
+      wave_lds_sync();
+      // Screening by all 64 lanes: lane (ri, kg) tests row ri against columns
+      // 4kg..4kg+3.  A column fails only if its dot product is below the
+      // row's k-th cosine times the two norms by a relative 2^-20, far beyond
+      // the rounding of either side, so it cannot beat the k-th entry exactly.
+      {
+        const float t_ws = __shfl(wsn, ri);
+        const int t_open = __shfl(open, ri);
+        const int off = (int)(c0 - (r0 + ri));  // column j is at offset j + off from the row
+        uint32_t bits = 0;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int j = 4 * kg + jj;
+          const int delta = j + off;
+          const int64_t cp = c0 + j;
+          const float b = band[wv][ri][j];
+          const float t = t_ws * tnrm[slot][j];
+          const bool in = row_ok & (delta != 0) & (delta <= w) & (-delta <= w) & (cp >= 0) & (cp < N);
+          const bool ok = in & ((t_open != 0) | (b >= t - fabsf(t) * 0x1p-20f));
+          bits |= (uint32_t)ok << jj;
         }
+        ((uint8_t*)&pass[wv][ri])[kg] = (uint8_t)bits;
       }
-      wsn = L.ws * own_n;
-      open = L.wi < 0;
+      wave_lds_sync();
+      uint32_t m = 0;
+      if (owner) {
+        const uint32_t x = pass[wv][l];
+        m = (x & 0xFu) | ((x >> 4) & 0xF0u) | ((x >> 8) & 0xF00u) | ((x >> 12) & 0xF000u);
+      }
+      if (__ballot(m != 0)) {
+        while (__ballot(m != 0)) {
+          if (m) {
+            const int j = __builtin_ctz(m);
+            m &= m - 1;
+            const float cs = band[wv][l][j] / (own_n * tnrm[slot][j]);
+            const int32_t c = tcid[slot][j];
+            if (L.wi < 0 || better(cs, c, L.ws, L.wi)) L.insert(k, cs, c);
+          }
+        }
+        wsn = L.ws * own_n;
+        open = L.wi < 0;
+      }
     }
-    wave_lds_sync();
+    if (q + 1 < nsteps) store((q + 1) & 1);
   }
   if (owner) {
 #pragma unroll

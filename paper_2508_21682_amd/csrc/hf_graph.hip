@@ -61,47 +61,59 @@ __device__ __forceinline__ bool better(float s1, int32_t c1, float s2, int32_t c
   return s1 > s2 || (s1 == s2 && (uint32_t)c1 < (uint32_t)c2);
 }
 
-// Top-k list of one row in registers, best first; (ws, wi) caches the k-th
-// entry so a rejected candidate costs one comparison.
+// Top-k list of one row in registers, best first.  Rows with k < KMAX
+// start with KMAX - k sentinels (+inf, id -2) that nothing displaces, so the
+// k-th entry is always the last slot; empty slots are (-inf, -1).
 template <int KMAX>
 struct TopList {
   float ls[KMAX];
   int32_t li[KMAX];
-  float ws;
-  int32_t wi;
-  __device__ __forceinline__ void refresh(int k) {
+  __device__ __forceinline__ float ws() const { return ls[KMAX - 1]; }
+  __device__ __forceinline__ int32_t wi() const { return li[KMAX - 1]; }
+  // slot i of the list holds entry i - (KMAX - k) of a k-list
+  __device__ __forceinline__ void load(const float* sc, const int32_t* id, int k, bool valid) {
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i)
-      if (i == k - 1) {
-        ws = ls[i];
-        wi = li[i];
+    for (int i = 0; i < KMAX; ++i) {
+      const int e = i - (KMAX - k);
+      ls[i] = e < 0 ? INFINITY : -INFINITY;
+      li[i] = e < 0 ? -2 : -1;
+      if (valid && e >= 0) {
+        ls[i] = sc[e];
+        li[i] = id[e];
       }
+    }
   }
-  __device__ __forceinline__ void insert(int k, float s, int32_t c) {
-    if (!(wi < 0 || better(s, c, ws, wi))) return;
+  __device__ __forceinline__ void save(float* sc, int32_t* id, int k) const {
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      const int e = i - (KMAX - k);
+      if (e >= 0) {
+        sc[e] = ls[i];
+        id[e] = li[i];
+      }
+    }
+  }
+  // (s, c) enters unless it is listed already; the slots it beats (a suffix
+  // of the list, empty slots included) shift down by one
+  __device__ __forceinline__ void insert(float s, int32_t c) {
     bool dup = false;
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) dup |= (i < k) && (li[i] == c);
+    for (int i = 0; i < KMAX; ++i) dup |= li[i] == c;
     if (dup) return;
-    bool placed = false;
+    bool prev = false;
+    float ps = 0.f;
+    int32_t pi = 0;
 #pragma unroll
-    for (int i = KMAX - 1; i >= 1; --i) {
-      if (i < k && !placed) {
-        if (li[i - 1] < 0 || better(s, c, ls[i - 1], li[i - 1])) {
-          ls[i] = ls[i - 1];
-          li[i] = li[i - 1];
-        } else {
-          ls[i] = s;
-          li[i] = c;
-          placed = true;
-        }
-      }
+    for (int i = 0; i < KMAX; ++i) {
+      const bool b = li[i] == -1 || better(s, c, ls[i], li[i]);
+      const float os = ls[i];
+      const int32_t oi = li[i];
+      ls[i] = b ? (prev ? ps : s) : os;
+      li[i] = b ? (prev ? pi : c) : oi;
+      ps = os;
+      pi = oi;
+      prev = b;
     }
-    if (!placed) {
-      ls[0] = s;
-      li[0] = c;
-    }
-    refresh(k);
   }
 };
 
@@ -129,7 +141,6 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   __shared__ int32_t tcid[2][16];
   __shared__ float tnrm[2][16];
   __shared__ float band[4][16][17];
-  __shared__ uint32_t pass[4][16];  // per row: byte g holds the pass bits of columns 4g..4g+3
   const int wv = threadIdx.x / 64, l = __lane_id();
   const int64_t R0 = (int64_t)blockIdx.x * 64;
   const int64_t r0 = R0 + 16 * wv;
@@ -144,20 +155,18 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   const bool owner = l < 16 && own < N;
   const int64_t own_id = owner ? (int64_t)order[own] : 0;
   const float own_n = owner ? ns[own] : 1.f;
+  L.load(gsc + own_id * k, gids + own_id * k, k, owner);
+  // row threshold in dot-product units, for the screening test of all lanes;
+  // lane (kg, ri) keeps copies for rows 4kg..4kg+3
+  float wsn = L.ws() * own_n;
+  int open = L.wi() < 0;
+  float rthr[4];
+  int ropen[4];
 #pragma unroll
-  for (int i = 0; i < KMAX; ++i) {
-    L.ls[i] = -INFINITY;
-    L.li[i] = -1;
-    if (owner && i < k) {
-      L.ls[i] = gsc[own_id * k + i];
-      L.li[i] = gids[own_id * k + i];
-    }
+  for (int r = 0; r < 4; ++r) {
+    rthr[r] = __shfl(wsn, 4 * kg + r);
+    ropen[r] = __shfl(open, 4 * kg + r);
   }
-  L.refresh(k);
-  // row threshold in dot-product units, for the screening test of all lanes
-  float wsn = L.ws * own_n;
-  int open = L.wi < 0;
-  const bool row_ok = arow >= 0;
   const int wr = (w + 15) / 16;
   const int nsteps = 4 + 2 * wr;
   const int64_t C0 = R0 - 16 * (int64_t)wr;  // first column of block 0
@@ -212,62 +221,56 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
         const half8 B = *(const half8*)(bt + 32 * s);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B, acc, 0, 0, 0);
       }
-      // D layout: lane l holds rows 4*(l/16)+r, column l%16
+      // D layout: lane (kg, ri) holds rows 4kg+r (r < 4) of column ri.
+      // Screening in registers: a pair fails only if its dot product is below
+      // the row's k-th cosine times the two norms by a relative 2^-20, far
+      // beyond the rounding of either side, so it cannot beat the k-th entry.
+      const float cn = tnrm[slot][ri];
+      const int off = (int)(c0 + ri - r0);  // column offset from row 0 of the tile
+      const int64_t cp = c0 + ri;
+      const bool col_ok = cp >= 0 && cp < N;
+      uint64_t bal[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) band[wv][4 * kg + r][ri] = acc[r];
-      wave_lds_sync();
-      // Screening by all 64 lanes: lane (ri, kg) tests row ri against columns
-      // 4kg..4kg+3.  A column fails only if its dot product is below the
-      // row's k-th cosine times the two norms by a relative 2^-20, far beyond
-      // the rounding of either side, so it cannot beat the k-th entry exactly.
-      {
-        const float t_ws = __shfl(wsn, ri);
-        const int t_open = __shfl(open, ri);
-        const int off = (int)(c0 - (r0 + ri));  // column j is at offset j + off from the row
-        uint32_t bits = 0;
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int j = 4 * kg + jj;
-          const int delta = j + off;
-          const int64_t cp = c0 + j;
-          const float b = band[wv][ri][j];
-          const float t = t_ws * tnrm[slot][j];
-          const bool in = row_ok & (delta != 0) & (delta <= w) & (-delta <= w) & (cp >= 0) & (cp < N);
-          const bool ok = in & ((t_open != 0) | (b >= t - fabsf(t) * 0x1p-20f));
-          bits |= (uint32_t)ok << jj;
-        }
-        ((uint8_t*)&pass[wv][ri])[kg] = (uint8_t)bits;
+      for (int r = 0; r < 4; ++r) {
+        const int R = 4 * kg + r;
+        const int delta = off - R;
+        const float t = rthr[r] * cn;
+        const bool in = col_ok & (r0 + R < N) & (delta != 0) & (delta <= w) & (-delta <= w);
+        bal[r] = __ballot(in & ((ropen[r] != 0) | (acc[r] >= t - fabsf(t) * 0x1p-20f)));
       }
-      wave_lds_sync();
+      // owner lane l (row l = 4g + r) takes bits 16g..16g+15 of ballot r
       uint32_t m = 0;
       if (owner) {
-        const uint32_t x = pass[wv][l];
-        m = (x & 0xFu) | ((x >> 4) & 0xF0u) | ((x >> 8) & 0xF00u) | ((x >> 12) & 0xF000u);
+        const int r = l & 3, g = l >> 2;
+        const uint64_t b = r == 0 ? bal[0] : (r == 1 ? bal[1] : (r == 2 ? bal[2] : bal[3]));
+        m = (uint32_t)(b >> (16 * g)) & 0xFFFFu;
       }
       if (__ballot(m != 0)) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) band[wv][4 * kg + r][ri] = acc[r];
+        wave_lds_sync();
         while (__ballot(m != 0)) {
           if (m) {
             const int j = __builtin_ctz(m);
             m &= m - 1;
             const float cs = band[wv][l][j] / (own_n * tnrm[slot][j]);
             const int32_t c = tcid[slot][j];
-            if (L.wi < 0 || better(cs, c, L.ws, L.wi)) L.insert(k, cs, c);
+            if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
           }
         }
-        wsn = L.ws * own_n;
-        open = L.wi < 0;
+        wsn = L.ws() * own_n;
+        open = L.wi() < 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          rthr[r] = __shfl(wsn, 4 * kg + r);
+          ropen[r] = __shfl(open, 4 * kg + r);
+        }
+        wave_lds_sync();
       }
     }
     if (q + 1 < nsteps) store((q + 1) & 1);
   }
-  if (owner) {
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i)
-      if (i < k) {
-        gsc[own_id * k + i] = L.ls[i];
-        gids[own_id * k + i] = L.li[i];
-      }
-  }
+  if (owner) L.save(gsc + own_id * k, gids + own_id * k, k);
 }
 
 unsigned grid_for(int64_t n) {

@@ -142,7 +142,11 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   __shared__ float tnrm[2][16];
   __shared__ float band[4][16][17];
   const int wv = threadIdx.x / 64, l = __lane_id();
-  const int64_t R0 = (int64_t)blockIdx.x * 64;
+  // workgroups are dealt to the eight XCDs in turn: give each XCD a
+  // contiguous run of position blocks so neighbours share its L2
+  const unsigned G = gridDim.x, per = G / 8, rem = G % 8, x8 = blockIdx.x % 8, j8 = blockIdx.x / 8;
+  const unsigned tileb = x8 < rem ? x8 * (per + 1) + j8 : rem * (per + 1) + (x8 - rem) * per + j8;
+  const int64_t R0 = (int64_t)tileb * 64;
   const int64_t r0 = R0 + 16 * wv;
   const int ri = l % 16, kg = l / 16;
   const int64_t arow = r0 + ri < N ? r0 + ri : -1;

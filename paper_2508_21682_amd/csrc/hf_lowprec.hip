@@ -76,7 +76,7 @@ __global__ void k_make_fp8(const T* __restrict__ X, int64_t N, int d, uint8_t* _
   if (__lane_id() == 0) scale[r] = s;
 }
 
-constexpr int LP_T = 256;
+constexpr int LP_T = 512;
 
 // PREC 1 = BF16 (KS = d/32 MFMA steps of K = 32), 2 = FP8 (KS = d/128 steps of K = 128).
 template <class T, int PREC, int KS>
@@ -117,7 +117,9 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
     if (l == 0) s_qmax[wv] = m;
     __syncthreads();
-    m = fmaxf(fmaxf(s_qmax[0], s_qmax[1]), fmaxf(s_qmax[2], s_qmax[3]));
+    m = 0.f;
+#pragma unroll
+    for (int i = 0; i < LP_T / 64; ++i) m = fmaxf(m, s_qmax[i]);
     qscale = m > 0.f ? __fdiv_rn(m, 448.0f) : 1.0f;
   }
   uint32_t qb[KS][PREC == 1 ? 4 : 8];

@@ -303,7 +303,7 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
 }
 
 // ------------------------------------------------------------------ rerank
-constexpr int RR_T = 256;
+constexpr int RR_T = 512;
 
 constexpr int RROWS = 4;
 

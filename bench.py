@@ -378,13 +378,17 @@ def bench_graph(args, hf, torch, ws):
     log("graph %.3f s, recall %.4f, stages %s" % (dt / args.steps, rec,
                                                    {k: round(v[0] / args.steps, 2) for k, v in stages.items()}))
     band_ms, band_n = stages["graph_band"]
-    # per band launch: every position reads its row once (768 B) plus its
-    # neighbours' rows through the cache, reads and writes its top-k list
+    # per band launch (one order): every position reads its re-laid row once
+    # (2d B), its norm and id (8 B), and reads and writes its top-k list
+    # (16k B); neighbours' rows come through the caches
     bytes_launch = N * (d * 2 + 4 + 4 + args.k * 8 * 2)
     achieved = bytes_launch / (band_ms / band_n * 1e-3) / 1e9
+    src = os.path.join(ROOT, "paper_2508_21682_amd", "csrc", "hf_graph.hip")
+    cfg = {"n": N, "orders": args.orders, "window": args.window, "k": args.k}
+    rec_t = measured_traffic("k_band_graph-3Mx384_counters.json", src, cfg)
     roof = {"bound": "hbm", "kernel": "k_band", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": bytes_launch,
-            "ms_per_launch": band_ms / band_n}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": rec_t[0] if rec_t else None,
+            "bytes_per_launch": bytes_launch, "ms_per_launch": band_ms / band_n}
     return {"metric": "kNN-graph build s (3Mx384, k=15)", "value": dt / args.steps, "unit": "s",
             "ms_per_step": dt * 1e3 / args.steps, "recall": rec, "higher_is_better": False,
             "config": {"workload": args.workload, "n": N, "d": d, "orders": args.orders,

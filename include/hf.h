@@ -290,8 +290,8 @@ hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash
  * 0 query codes, 1 query sketches, 2 descend, 3 hamming, 4 select, 5 rerank,
  * 6 graph sort, 7 graph band, 8 build sort, 9 build trie, 10 build sketch,
  * 11 lowprec score, 12 graph hamming band, 13 graph list merge, 14 graph
- * final cosine top-k. */
-#define HF_N_STAGES 15
+ * final cosine top-k, 15 graph row gather. */
+#define HF_N_STAGES 16
 hf_status hf_timing_enable(int32_t on);
 /* Waits for the recorded events, writes the summed milliseconds and launch
  * counts of every stage since the last read (arrays of HF_N_STAGES), clears. */

@@ -32,7 +32,7 @@ EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_qu
            "hf_search_lowprec_debug", "hf_audit_scores", "hf_lhash_create", "hf_lhash_free", "hf_lhash_get",
            "hf_lhash_encode", "hf_lhash_grad", "hf_lhash_train", "hf_forest_set_sketch",
            "hf_knn_graph_debug"]
-N_STAGES = 15
+N_STAGES = 16
 
 
 class HFError(RuntimeError):

@@ -413,9 +413,12 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
       StageTimer tm(ST_GSORT, s);
       HF_TRY(hilbert_sort_dev(codes, msb, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
     }
+    {
+      StageTimer tg(ST_GGATHER, s);
+      k_gather_sorted<<<grid_for(N * (d / 8)), 256, 0, s>>>(X, nrm, order, N, d, Xs, ns);
+      HF_LAUNCH_CHECK();
+    }
     StageTimer tm(ST_GBAND, s);
-    k_gather_sorted<<<grid_for(N * (d / 8)), 256, 0, s>>>(X, nrm, order, N, d, Xs, ns);
-    HF_LAUNCH_CHECK();
     if (p.k <= 16)
       HF_TRY(launch_band<16>(ks, Xs, N, d, order, ns, (int)p.window, (int)p.k, ids, scores, s));
     else

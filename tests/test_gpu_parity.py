@@ -200,6 +200,12 @@ def test_forest_edge_cases(hf, orc):
     _forest_case(hf, orc, x, q, T=2, M=3, seed=9, sk_seed=10, params=[(17, 11, 1, 4)])
 
 
+def test_forest_search_large_candidate_sets(hf, orc):
+    """16 trees x windows of 2,048-2,500 (up to 40,000 entries per query)."""
+    x, q = datagen.mixture(30000, 64, 24, 0.1, 55, dtype=np.float16, query_seed=56, nq=160)
+    _forest_case(hf, orc, x, q, T=16, M=100, seed=13, sk_seed=14, params=[(2500, 600, 2, 20), (2048, 300, 0, 10)])
+
+
 def test_forest_duplicates_overflow_selection(hf, orc):
     """All points identical: one oversized leaf, every candidate at Hamming 0,
     more candidates than the selection buffer holds (position-split path)."""

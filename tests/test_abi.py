@@ -72,6 +72,33 @@ def test_invalid_arguments_rejected_on_host(hf):
     assert L.hf_knn_graph(dummy, 0, 100, 8, C.byref(g), dummy, dummy, None) == 1  # k2 < k
 
 
+def test_graph_arguments_rejected_on_host(hf):
+    """Every graph argument check happens before any device work."""
+    L = hf.lib()
+    dummy = C.c_void_p(256)
+
+    def gp(n=4, w=8, k=15, k2=0, sketch=0, lhash=None):
+        return hf.GraphParams(C.sizeof(hf.GraphParams), n, w, k, k2, hf.HF_QUANT_AUTO, sketch, 1, 2, lhash)
+
+    def call(g, X=dummy, dtype=0, N=1000, d=64):
+        return L.hf_knn_graph(X, dtype, N, d, C.byref(g), dummy, dummy, None)
+
+    assert call(gp(k2=257)) == 1                  # k2 above 256
+    assert call(gp(w=513)) == 1                   # window above 512
+    assert call(gp(k=33)) == 1                    # k above 32
+    assert call(gp(n=0)) == 1                     # no orders
+    assert call(gp(k2=20, sketch=7)) == 1         # unknown sketch kind
+    assert call(gp(k2=20, sketch=1)) == 1         # learned sketches without a hash
+    assert b"hash" in L.hf_last_error()
+    assert call(gp(), X=C.c_void_p(258)) == 1     # rows not 16-byte aligned
+    assert call(gp(), dtype=1) == 6               # fp32 rows: unsupported
+    assert call(gp(), d=60) == 6                  # d not a multiple of 8
+    g = gp()
+    assert L.hf_knn_graph_debug(dummy, 0, 1000, 64, C.byref(g), dummy, dummy, dummy, None) == 1  # k2 = 0
+    g = gp(k2=20)
+    assert L.hf_knn_graph_debug(dummy, 0, 1000, 64, C.byref(g), dummy, dummy, None, None) == 1   # no C2 buffer
+
+
 def test_invalid_handle(hf):
     L = hf.lib()
     info = hf.ForestInfo()

@@ -6,11 +6,11 @@
 // registers as the A operand of v_mfma_f32_16x16x32_f16; the rows of each
 // 16-position block within +-w stream through a shared LDS tile as the B
 // operand, so every MFMA tile is a 16x16 block of dot products along the
-// band.  All 64 lanes screen the tile's pairs against each row's current k-th
-// entry; cosines (FP32 accumulate, FP32 norms) of the survivors with
-// 0 < |i-j| <= w are merged by the row's owner lane into that point's top-k
-// list (cosine desc, id asc), held in registers while the wave runs and in
-// HBM between orders.  A candidate already in the list is skipped; one that
+// band.  All 64 lanes screen the tile's pairs against each row's k-th entry;
+// cosines (FP32 accumulate, FP32 norms) of the survivors with 0 < |i-j| <= w
+// are queued per row in LDS and merged by the row's owner lane into that
+// point's top-k list (cosine desc, id asc), held in registers while the wave
+// runs and in HBM between orders.  A candidate already in the list is skipped; one that
 // was evicted earlier is evicted again (its score is fixed), so the list
 // stays the top-k of the union of all windows seen.
 #include <math.h>
@@ -140,7 +140,10 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   __shared__ __attribute__((aligned(16))) _Float16 tile[2][16 * RS];
   __shared__ int32_t tcid[2][16];
   __shared__ float tnrm[2][16];
-  __shared__ float band[4][16][17];
+  constexpr int QCAP = 64;  // queued pairs per row
+  __shared__ float qcs[4][16][QCAP];
+  __shared__ int32_t qid[4][16][QCAP];
+  __shared__ uint32_t qn[4][16];
   const int wv = threadIdx.x / 64, l = __lane_id();
   // workgroups are dealt to the eight XCDs in turn: give each XCD a
   // contiguous run of position blocks so neighbours share its L2
@@ -164,13 +167,39 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   // lane (kg, ri) keeps copies for rows 4kg..4kg+3
   float wsn = L.ws() * own_n;
   int open = L.wi() < 0;
-  float rthr[4];
+  float rthr[4], rown[4];
   int ropen[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     rthr[r] = __shfl(wsn, 4 * kg + r);
     ropen[r] = __shfl(open, 4 * kg + r);
+    rown[r] = __shfl(own_n, 4 * kg + r);
   }
+  // Pairs that pass the screening wait in a per-row queue; the owners merge
+  // the queues into their lists when one fills up and after the last step.
+  // The lists end as the top-k of all candidates whatever the order of the
+  // merges, and a late threshold only lets more pairs through the screening.
+  if (l < 16) qn[wv][l] = 0;
+  wave_lds_sync();
+  auto drain = [&]() {
+    const uint32_t n = owner ? qn[wv][l] : 0u;
+    for (uint32_t i = 0; __ballot(i < n); ++i) {
+      if (i < n) {
+        const float cs = qcs[wv][l][i];
+        const int32_t c = qid[wv][l][i];
+        if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
+      }
+    }
+    if (l < 16) qn[wv][l] = 0;
+    wsn = L.ws() * own_n;
+    open = L.wi() < 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      rthr[r] = __shfl(wsn, 4 * kg + r);
+      ropen[r] = __shfl(open, 4 * kg + r);
+    }
+    wave_lds_sync();
+  };
   const int wr = (w + 15) / 16;
   const int nsteps = 4 + 2 * wr;
   const int64_t C0 = R0 - 16 * (int64_t)wr;  // first column of block 0
@@ -233,47 +262,27 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
       const int off = (int)(c0 + ri - r0);  // column offset from row 0 of the tile
       const int64_t cp = c0 + ri;
       const bool col_ok = cp >= 0 && cp < N;
-      uint64_t bal[4];
+      const int32_t cid = tcid[slot][ri];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int R = 4 * kg + r;
         const int delta = off - R;
         const float t = rthr[r] * cn;
         const bool in = col_ok & (r0 + R < N) & (delta != 0) & (delta <= w) & (-delta <= w);
-        bal[r] = __ballot(in & ((ropen[r] != 0) | (acc[r] >= t - fabsf(t) * 0x1p-20f)));
-      }
-      // owner lane l (row l = 4g + r) takes bits 16g..16g+15 of ballot r
-      uint32_t m = 0;
-      if (owner) {
-        const int r = l & 3, g = l >> 2;
-        const uint64_t b = r == 0 ? bal[0] : (r == 1 ? bal[1] : (r == 2 ? bal[2] : bal[3]));
-        m = (uint32_t)(b >> (16 * g)) & 0xFFFFu;
-      }
-      if (__ballot(m != 0)) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) band[wv][4 * kg + r][ri] = acc[r];
-        wave_lds_sync();
-        while (__ballot(m != 0)) {
-          if (m) {
-            const int j = __builtin_ctz(m);
-            m &= m - 1;
-            const float cs = band[wv][l][j] / (own_n * tnrm[slot][j]);
-            const int32_t c = tcid[slot][j];
-            if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
-          }
+        if (in & ((ropen[r] != 0) | (acc[r] >= t - fabsf(t) * 0x1p-20f))) {
+          // the exact cosine, as the row's owner would compute it, queued
+          const uint32_t j = atomicAdd(&qn[wv][R], 1u);
+          qcs[wv][R][j] = acc[r] / (rown[r] * cn);
+          qid[wv][R][j] = cid;
         }
-        wsn = L.ws() * own_n;
-        open = L.wi() < 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          rthr[r] = __shfl(wsn, 4 * kg + r);
-          ropen[r] = __shfl(open, 4 * kg + r);
-        }
-        wave_lds_sync();
       }
+      wave_lds_sync();
+      // a step queues at most 16 per row: drain rows past QCAP - 16
+      if (__ballot(owner && qn[wv][l] > (uint32_t)(QCAP - 16))) drain();
     }
     if (q + 1 < nsteps) store((q + 1) & 1);
   }
+  if (r0 < N) drain();
   if (owner) L.save(gsc + own_id * k, gids + own_id * k, k);
 }
 

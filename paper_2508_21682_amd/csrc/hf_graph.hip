@@ -1,6 +1,9 @@
 // k-NN graph from windows along several Hilbert orders (Section 4.1,
 // Algorithm 2).  Per order: Hilbert sort of all points, then a band kernel.
 //
+// Orders are pipelined: a second stream sorts and gathers order t+1 while the
+// band kernel of order t runs on the caller's stream.
+//
 // Band kernel: a workgroup owns 64 consecutive positions of the order, a
 // wavefront 16 of them.  Their rows (fp16, gathered through the order) stay in
 // registers as the A operand of v_mfma_f32_16x16x32_f16; the rows of each
@@ -386,17 +389,35 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     set_error("graph band kernel: d > 1024 not built");
     return HF_ERR_UNSUPPORTED;
   }
+  // A second stream sorts and gathers order t+1 while the band kernel of
+  // order t runs: orders, re-laid rows and norms are double-buffered.
+  struct Pipe {
+    hipStream_t s2 = nullptr;
+    hipEvent_t ready = nullptr, sorted[2] = {nullptr, nullptr}, banded[2] = {nullptr, nullptr};
+    ~Pipe() {
+      if (s2) (void)hipStreamSynchronize(s2);
+      for (hipEvent_t e : {ready, sorted[0], sorted[1], banded[0], banded[1]})
+        if (e) (void)hipEventDestroy(e);
+      if (s2) (void)hipStreamDestroy(s2);
+    }
+  } pp;
+  HIP_TRY(hipStreamCreateWithFlags(&pp.s2, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&pp.ready, &pp.sorted[0], &pp.sorted[1], &pp.banded[0], &pp.banded[1]})
+    HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  hipStream_t s2 = pp.s2;
   Workspace ws(s);
   uint8_t* codes;
   float* nrm;
-  uint32_t* order;
-  __half* Xs;
-  float* ns;
-  HF_TRY(ws.alloc(&Xs, (size_t)(N * d)));
-  HF_TRY(ws.alloc(&ns, (size_t)N));
+  uint32_t* order[2];
+  __half* Xs[2];
+  float* ns[2];
+  for (int b = 0; b < 2; ++b) {
+    HF_TRY(ws.alloc(&Xs[b], (size_t)(N * d)));
+    HF_TRY(ws.alloc(&ns[b], (size_t)N));
+    HF_TRY(ws.alloc(&order[b], (size_t)N));
+  }
   HF_TRY(ws.alloc(&codes, (size_t)(N * d)));
   HF_TRY(ws.alloc(&nrm, (size_t)N));
-  HF_TRY(ws.alloc(&order, (size_t)N));
   HF_TRY(quantize(X, HF_F16, N * d, e, codes, s));
   uint32_t* msb = nullptr;
   if (msb_words(d) > 0) {
@@ -416,23 +437,41 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   HF_TRY(ws.alloc(&drefl, (size_t)T * d));
   HIP_TRY(hipMemcpyAsync(dperm, perm.data(), 4 * (size_t)T * d, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(drefl, refl.data(), (size_t)T * d, hipMemcpyHostToDevice, s));
-  for (int t = 0; t < T; ++t) {
-    Workspace wt(s);
+  HIP_TRY(hipEventRecord(pp.ready, s));
+  HIP_TRY(hipStreamWaitEvent(s2, pp.ready, 0));
+  // sort and gather order t into buffer t & 1 on the second stream
+  auto prepare = [&](int t) -> hf_status {
+    const int b = t & 1;
+    if (t >= 2) HIP_TRY(hipStreamWaitEvent(s2, pp.banded[b], 0));  // band t-2 is done with b
     {
-      StageTimer tm(ST_GSORT, s);
-      HF_TRY(hilbert_sort_dev(codes, msb, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order, nullptr, wt));
+      Workspace wt(s2);
+      StageTimer tm(ST_GSORT, s2);
+      HF_TRY(hilbert_sort_dev(codes, msb, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order[b], nullptr,
+                              wt));
     }
     {
-      StageTimer tg(ST_GGATHER, s);
-      k_gather_sorted<<<grid_for(N * (d / 8)), 256, 0, s>>>(X, nrm, order, N, d, Xs, ns);
+      StageTimer tg(ST_GGATHER, s2);
+      k_gather_sorted<<<grid_for(N * (d / 8)), 256, 0, s2>>>(X, nrm, order[b], N, d, Xs[b], ns[b]);
       HF_LAUNCH_CHECK();
     }
-    StageTimer tm(ST_GBAND, s);
-    if (p.k <= 16)
-      HF_TRY(launch_band<16>(ks, Xs, N, d, order, ns, (int)p.window, (int)p.k, ids, scores, s));
-    else
-      HF_TRY(launch_band<32>(ks, Xs, N, d, order, ns, (int)p.window, (int)p.k, ids, scores, s));
+    HIP_TRY(hipEventRecord(pp.sorted[b], s2));
+    return HF_OK;
+  };
+  HF_TRY(prepare(0));
+  for (int t = 0; t < T; ++t) {
+    const int b = t & 1;
+    HIP_TRY(hipStreamWaitEvent(s, pp.sorted[b], 0));
+    {
+      StageTimer tm(ST_GBAND, s);
+      if (p.k <= 16)
+        HF_TRY(launch_band<16>(ks, Xs[b], N, d, order[b], ns[b], (int)p.window, (int)p.k, ids, scores, s));
+      else
+        HF_TRY(launch_band<32>(ks, Xs[b], N, d, order[b], ns[b], (int)p.window, (int)p.k, ids, scores, s));
+    }
+    HIP_TRY(hipEventRecord(pp.banded[b], s));
+    if (t + 1 < T) HF_TRY(prepare(t + 1));
   }
+  HIP_TRY(hipStreamSynchronize(s2));
   HIP_TRY(hipStreamSynchronize(s));
   return HF_OK;
 }

@@ -102,8 +102,8 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
 }
 
 // ------------------------------------------------------------------ select
-constexpr int SEL_T = 1024;
-constexpr int CAP = 16384;
+constexpr int SEL_T = 512;
+constexpr int CAP = 8192;
 constexpr int NBK = 1024;
 
 // Visits every window entry of one query: the Hamming values are read 8 at a

@@ -391,6 +391,9 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   }
   // A second stream sorts and gathers order t+1 while the band kernel of
   // order t runs: orders, re-laid rows and norms are double-buffered.
+  // (the workspace is declared first so that it is released last, after the
+  // guard below has waited for the second stream)
+  Workspace ws(s);
   struct Pipe {
     hipStream_t s2 = nullptr;
     hipEvent_t ready = nullptr, sorted[2] = {nullptr, nullptr}, banded[2] = {nullptr, nullptr};
@@ -405,7 +408,6 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   for (hipEvent_t* e : {&pp.ready, &pp.sorted[0], &pp.sorted[1], &pp.banded[0], &pp.banded[1]})
     HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   hipStream_t s2 = pp.s2;
-  Workspace ws(s);
   uint8_t* codes;
   float* nrm;
   uint32_t* order[2];

@@ -156,7 +156,8 @@ hf_status hf_srp_sketch(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
  * vectors re-laid in master order, then n leaf-compressed Hilbert trees whose
  * permutations hold master positions.  The forest keeps its own copies; X_dev
  * is not retained.  *out receives a handle to free with hf_forest_free.
- * Synchronises. */
+ * Synchronises.  With HF_PROGRESS set in the environment, one line per tree
+ * goes to stderr. */
 hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
                           const hf_forest_params* params, void* stream, hf_forest** out);
 void hf_forest_free(hf_forest* f);

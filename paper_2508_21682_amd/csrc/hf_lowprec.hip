@@ -152,6 +152,9 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
     const uint32_t e = e0 + (l % 16);
     const bool ok = e < E;
     const uint32_t p = ok ? epos(st, off, n2, e) : 0u;
+    // FP8: the row's scale, fetched with its codes (lane l holds row l % 16)
+    float rs = 1.f;
+    if constexpr (PREC == 2) rs = ok ? s8[p] : 1.f;
     float4v acc = {0.f, 0.f, 0.f, 0.f};
     if constexpr (PREC == 1) {
       const uint16_t* row = (const uint16_t*)Xlp + (int64_t)p * d;
@@ -178,13 +181,16 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
       }
     }
     // lane l holds rows 4*(l/16)+r of the block (every column is the same)
+    float rsc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rsc[r] = __shfl(rs, 4 * g + r);
     if (l % 16 == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const uint32_t er = e0 + 4 * g + r;
         if (er < E) {
           float v = acc[r];
-          if constexpr (PREC == 2) v = v * (s8[epos(st, off, n2, er)] * qscale);
+          if constexpr (PREC == 2) v = v * (rsc[r] * qscale);
           ekey[er] = ~float_to_ordered(v);
         }
       }

@@ -483,6 +483,7 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   // the second stage runs in batches of queries sized to bound scratch memory
   const int64_t per_q = ((int64_t)T * len + 7) / 8 * 8;  // 16-byte aligned rows of distances
   int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1ll << 31) / (per_q * 2 + 1)));
+  batch = ceil_div(nq, ceil_div(nq, batch));  // equal batches
   uint16_t* ham;
   uint32_t *hist, *c2 = c2_out;
   int32_t* c2n = c2n_out;

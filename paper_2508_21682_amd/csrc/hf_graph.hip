@@ -128,22 +128,24 @@ __device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t
 
 // A workgroup (four wavefronts) owns 64 consecutive positions; wavefront v
 // owns rows R0+16v .. +15.  Column blocks of 16 positions stream through a
-// double-buffered LDS tile shared by the four wavefronts (loaded once, one
-// step ahead, 16-byte coalesced); wavefront v uses blocks v .. v+2*wr of the
-// workgroup's 4+2*wr.  Rows are padded by 16 bytes in LDS so the 16 lanes
-// reading one column fragment hit distinct banks.
+// double-buffered LDS tile shared by the four wavefronts, BPS blocks per
+// step (loaded once, one step ahead, 16-byte coalesced); wavefront v uses
+// blocks v .. v+2*wr of the workgroup's 4+2*wr.  Rows are padded by 16 bytes
+// in LDS so the 16 lanes reading one column fragment hit distinct banks.
 template <int KMAX, int KS>
 __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int64_t N, int d,
                                               const uint32_t* __restrict__ order,
                                               const float* __restrict__ ns, int w, int k,
                                               int32_t* __restrict__ gids, float* __restrict__ gsc) {
+  constexpr int BPS = 2;           // column blocks per step
+  constexpr int TR = 16 * BPS;     // tile rows
   constexpr int RS = KS * 32 + 8;  // LDS row stride (halves)
   constexpr int CPR = KS * 4;      // 16-byte chunks per tile row
-  constexpr int CH = (16 * CPR + 255) / 256;  // chunks per thread per tile
-  __shared__ __attribute__((aligned(16))) _Float16 tile[2][16 * RS];
-  __shared__ int32_t tcid[2][16];
-  __shared__ float tnrm[2][16];
-  constexpr int QCAP = 64;  // queued pairs per row
+  constexpr int CH = (TR * CPR + 255) / 256;  // chunks per thread per tile
+  __shared__ __attribute__((aligned(16))) _Float16 tile[2][TR * RS];
+  __shared__ int32_t tcid[2][TR];
+  __shared__ float tnrm[2][TR];
+  constexpr int QCAP = 32;  // queued pairs per row (a block adds at most 16)
   __shared__ float qcs[4][16][QCAP];
   __shared__ int32_t qid[4][16][QCAP];
   __shared__ uint32_t qn[4][16];
@@ -166,9 +168,12 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   const int64_t own_id = owner ? (int64_t)order[own] : 0;
   const float own_n = owner ? ns[own] : 1.f;
   L.load(gsc + own_id * k, gids + own_id * k, k, owner);
-  // row threshold in dot-product units, for the screening test of all lanes;
-  // lane (kg, ri) keeps copies for rows 4kg..4kg+3
-  float wsn = L.ws() * own_n;
+  // row threshold in dot-product units, lowered by a relative 2^-20 (far
+  // beyond the rounding of either side, so a pair below it cannot beat the
+  // k-th entry), for the screening test of all lanes; lane (kg, ri) keeps
+  // copies for rows 4kg..4kg+3
+  auto margin = [](float x) { return x - fabsf(x) * 0x1p-20f; };
+  float wsn = margin(L.ws() * own_n);
   int open = L.wi() < 0;
   float rthr[4], rown[4];
   int ropen[4];
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
       }
     }
     if (l < 16) qn[wv][l] = 0;
-    wsn = L.ws() * own_n;
+    wsn = margin(L.ws() * own_n);
     open = L.wi() < 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -204,25 +209,38 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
     wave_lds_sync();
   };
   const int wr = (w + 15) / 16;
-  const int nsteps = 4 + 2 * wr;
+  const int nsteps = (4 + 2 * wr + BPS - 1) / BPS;
   const int64_t C0 = R0 - 16 * (int64_t)wr;  // first column of block 0
-  // cooperative tile load: chunk x of the tile is row x / CPR, halves 8*(x % CPR)
+  // cooperative tile load: chunk x of the tile is row x / CPR, halves 8*(x % CPR).
+  // A tile of whole rows inside the array (d = 32 KS) is one contiguous run
+  // of memory: chunk x is 16-byte vector x from the tile's first row.
   uint4 stg[CH];
   int32_t scid = -1;
   float snrm = 1.f;
+  const bool dense = d == KS * 32;
   auto fetch = [&](int q) {
-    const int64_t cb0 = C0 + 16 * (int64_t)q;
+    const int64_t cb0 = C0 + TR * (int64_t)q;
+    if (dense && cb0 >= 0 && cb0 + TR <= N) {
+      const uint4* src = (const uint4*)(Xs + cb0 * d);
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int x = threadIdx.x + 256 * i;
-      const int rr = x / CPR, k0 = 8 * (x % CPR);
-      const int64_t row = cb0 + rr;
-      stg[i] = make_uint4(0, 0, 0, 0);
-      if (x < 16 * CPR && row >= 0 && row < N && k0 < d) stg[i] = *(const uint4*)(Xs + row * d + k0);
+      for (int i = 0; i < CH; ++i) {
+        const int x = threadIdx.x + 256 * i;
+        stg[i] = make_uint4(0, 0, 0, 0);
+        if ((i + 1) * 256 <= TR * CPR || x < TR * CPR) stg[i] = src[x];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const int x = threadIdx.x + 256 * i;
+        const int rr = x / CPR, k0 = 8 * (x % CPR);
+        const int64_t row = cb0 + rr;
+        stg[i] = make_uint4(0, 0, 0, 0);
+        if (x < TR * CPR && row >= 0 && row < N && k0 < d) stg[i] = *(const uint4*)(Xs + row * d + k0);
+      }
     }
     scid = -1;
     snrm = 1.f;
-    if (threadIdx.x < 16) {
+    if (threadIdx.x < TR) {
       const int64_t row = cb0 + threadIdx.x;
       if (row >= 0 && row < N) {
         scid = (int32_t)order[row];
@@ -234,9 +252,9 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
 #pragma unroll
     for (int i = 0; i < CH; ++i) {
       const int x = threadIdx.x + 256 * i;
-      if (x < 16 * CPR) *(uint4*)(&tile[slot][(x / CPR) * RS + 8 * (x % CPR)]) = stg[i];
+      if (x < TR * CPR) *(uint4*)(&tile[slot][(x / CPR) * RS + 8 * (x % CPR)]) = stg[i];
     }
-    if (threadIdx.x < 16) {
+    if (threadIdx.x < TR) {
       tcid[slot][threadIdx.x] = scid;
       tnrm[slot][threadIdx.x] = snrm;
     }
@@ -246,42 +264,60 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   for (int q = 0; q < nsteps; ++q) {
     __syncthreads();  // tile q is in slot q & 1; slot (q + 1) & 1 is free
     if (q + 1 < nsteps) fetch(q + 1);
-    const int cb = q - wv;
+#pragma unroll
+    for (int hb = 0; hb < BPS; ++hb) {
+    const int blk = BPS * q + hb;
+    const int cb = blk - wv;
     if (cb >= 0 && cb <= 2 * wr && r0 < N) {
       const int slot = q & 1;
-      const int64_t c0 = C0 + 16 * (int64_t)q;
+      const int64_t c0 = C0 + 16 * (int64_t)blk;
       float4v acc = {0.f, 0.f, 0.f, 0.f};
-      const _Float16* bt = &tile[slot][ri * RS + 8 * kg];
+      const _Float16* bt = &tile[slot][(16 * hb + ri) * RS + 8 * kg];
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const half8 B = *(const half8*)(bt + 32 * s);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B, acc, 0, 0, 0);
       }
       // D layout: lane (kg, ri) holds rows 4kg+r (r < 4) of column ri.
-      // Screening in registers: a pair fails only if its dot product is below
-      // the row's k-th cosine times the two norms by a relative 2^-20, far
-      // beyond the rounding of either side, so it cannot beat the k-th entry.
-      const float cn = tnrm[slot][ri];
-      const int off = (int)(c0 + ri - r0);  // column offset from row 0 of the tile
-      const int64_t cp = c0 + ri;
-      const bool col_ok = cp >= 0 && cp < N;
-      const int32_t cid = tcid[slot][ri];
+      // Screening in registers against the rows' thresholds; the band and
+      // array bounds are tested per pair only in blocks that cross them.
+      const float cn = tnrm[slot][16 * hb + ri];
+      const int64_t o = c0 - r0;  // pair offsets of the block: o - 15 .. o + 15
+      const bool inner = c0 >= 0 && c0 + 16 <= N && r0 + 16 <= N &&
+                         ((o >= 16 && o + 15 <= w) || (o <= -16 && o - 15 >= -w));
+      bool pass[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int R = 4 * kg + r;
-        const int delta = off - R;
-        const float t = rthr[r] * cn;
-        const bool in = col_ok & (r0 + R < N) & (delta != 0) & (delta <= w) & (-delta <= w);
-        if (in & ((ropen[r] != 0) | (acc[r] >= t - fabsf(t) * 0x1p-20f))) {
-          // the exact cosine, as the row's owner would compute it, queued
-          const uint32_t j = atomicAdd(&qn[wv][R], 1u);
-          qcs[wv][R][j] = acc[r] / (rown[r] * cn);
-          qid[wv][R][j] = cid;
+      for (int r = 0; r < 4; ++r) pass[r] = (ropen[r] != 0) | (acc[r] >= rthr[r] * cn);
+      if (!inner) {
+        const int off = (int)o + ri;  // column offset from row 0 of the tile
+        const bool col_ok = c0 + ri >= 0 && c0 + ri < N;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int R = 4 * kg + r;
+          const int delta = off - R;
+          pass[r] &= col_ok & (r0 + R < N) & (delta != 0) & (delta <= w) & (-delta <= w);
         }
       }
-      wave_lds_sync();
-      // a step queues at most 16 per row: drain rows past QCAP - 16
-      if (__ballot(owner && qn[wv][l] > (uint32_t)(QCAP - 16))) drain();
+      if (__ballot(pass[0] | pass[1] | pass[2] | pass[3])) {
+        const int32_t cid = tcid[slot][16 * hb + ri];
+        bool full = false;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (pass[r]) {
+            // the exact cosine, as the row's owner would compute it, queued
+            const int R = 4 * kg + r;
+            const uint32_t j = atomicAdd(&qn[wv][R], 1u);
+            qcs[wv][R][j] = acc[r] / (rown[r] * cn);
+            qid[wv][R][j] = cid;
+            full |= j >= (uint32_t)(QCAP - 16);
+          }
+        }
+        wave_lds_sync();
+        // a block queues at most 16 per row: drain once a row holds more
+        // than QCAP - 16
+        if (__ballot(full)) drain();
+      }
+    }
     }
     if (q + 1 < nsteps) store((q + 1) & 1);
   }

@@ -46,20 +46,6 @@ __global__ void k_init_lists(int32_t* __restrict__ ids, float* __restrict__ sc, 
   }
 }
 
-// Rows (and their norms) re-laid in the order's sequence so the band tiles
-// read contiguous memory.
-__global__ void k_gather_sorted(const __half* __restrict__ X, const float* __restrict__ nrm,
-                                const uint32_t* __restrict__ order, int64_t N, int d,
-                                __half* __restrict__ Xs, float* __restrict__ ns) {
-  const int64_t nv = d / 8;  // 16-byte vectors per row
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N * nv; i += (int64_t)gridDim.x * 256) {
-    const int64_t r = i / nv, c = i - r * nv;
-    const uint32_t id = order[r];
-    ((uint4*)Xs)[r * nv + c] = ((const uint4*)(X + (int64_t)id * d))[c];
-    if (c == 0) ns[r] = nrm[id];
-  }
-}
-
 __device__ __forceinline__ bool better(float s1, int32_t c1, float s2, int32_t c2) {
   return s1 > s2 || (s1 == s2 && (uint32_t)c1 < (uint32_t)c2);
 }
@@ -126,25 +112,45 @@ __device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t
   return __builtin_bit_cast(half8, raw);
 }
 
+// Pairs sent to a point by the band kernel of one order, for its owner to
+// merge in the next order: per point a count and up to w (cosine, id)
+// entries.
+struct Mailbox {
+  uint32_t* n;
+  uint2* e;
+};
+
 // A workgroup (four wavefronts) owns 64 consecutive positions; wavefront v
 // owns rows R0+16v .. +15.  Column blocks of 16 positions stream through a
 // double-buffered LDS tile shared by the four wavefronts, BPS blocks per
-// step (loaded once, one step ahead, 16-byte coalesced); wavefront v uses
-// blocks v .. v+2*wr of the workgroup's 4+2*wr.  Rows are padded by 16 bytes
-// in LDS so the 16 lanes reading one column fragment hit distinct banks.
-template <int KMAX, int KS>
-__global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int64_t N, int d,
+// step, fetched two steps ahead (16-byte coalesced).  Rows are padded by 16
+// bytes in LDS so the 16 lanes reading one column fragment hit distinct
+// banks.  Rows are read from X through the order: the point ids of a tile
+// reach LDS three steps ahead of its rows, so no global load waits on another.
+//
+// SYM: each pair of the band is computed once, by the owner of its lower
+// position i: columns i+1 .. i+w only (blocks v .. v+wr of 4+wr).  The pair
+// is screened against both points' thresholds (the column point's is read
+// from its list in HBM: any value it held is a valid lower bound); the row
+// side is queued as below, the column side goes to the column point's
+// mailbox `mo`, which its owner merges in the next order (`mi`, whose counts
+// it clears).  Otherwise every row meets columns i-w .. i+w (blocks
+// v .. v+2wr of 4+2wr) and pairs are computed from both sides.
+template <int KMAX, int KS, bool SYM>
+__global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(const __half* __restrict__ X, int64_t N, int d,
                                               const uint32_t* __restrict__ order,
-                                              const float* __restrict__ ns, int w, int k,
-                                              int32_t* __restrict__ gids, float* __restrict__ gsc) {
+                                              const float* __restrict__ nrm, int w, int k,
+                                              int32_t* __restrict__ gids, float* __restrict__ gsc,
+                                              Mailbox mi, Mailbox mo) {
   constexpr int BPS = 2;           // column blocks per step
   constexpr int TR = 16 * BPS;     // tile rows
   constexpr int RS = KS * 32 + 8;  // LDS row stride (halves)
   constexpr int CPR = KS * 4;      // 16-byte chunks per tile row
   constexpr int CH = (TR * CPR + 255) / 256;  // chunks per thread per tile
   __shared__ __attribute__((aligned(16))) _Float16 tile[2][TR * RS];
-  __shared__ int32_t tcid[2][TR];
+  __shared__ int32_t tcid[3][TR];  // point ids of the tile rows of step q: slot q % 3
   __shared__ float tnrm[2][TR];
+  __shared__ float tthr[2][TR];    // SYM: column thresholds in dot units / row norm
   constexpr int QCAP = 32;  // queued pairs per row (a block adds at most 16)
   __shared__ float qcs[4][16][QCAP];
   __shared__ int32_t qid[4][16][QCAP];
@@ -157,22 +163,118 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
   const int64_t R0 = (int64_t)tileb * 64;
   const int64_t r0 = R0 + 16 * wv;
   const int ri = l % 16, kg = l / 16;
-  const int64_t arow = r0 + ri < N ? r0 + ri : -1;
-  half8 A[KS];
+  const int wr = (w + 15) / 16;
+  const int cbmax = SYM ? wr : 2 * wr;  // a wavefront's blocks: v .. v + cbmax
+  const int nsteps = (4 + cbmax + BPS - 1) / BPS;
+  const int64_t C0 = SYM ? R0 : R0 - 16 * (int64_t)wr;  // first column of block 0
+  auto margin = [](float x) { return x - fabsf(x) * 0x1p-20f; };
+
+  // Tile pipeline.  Chunk x of a tile is row x / CPR, halves 8*(x % CPR).
+  // The ids of the rows of step q reach LDS slot q % 3 two steps ahead; the
+  // rows are fetched into registers at the start of the step before theirs
+  // and stored to LDS at its end (the barriers between steps order LDS only,
+  // so the loads stay in flight through the step's work).
+  // Every global load of the pipeline is issued unconditionally, by every
+  // thread and at every step (out-of-range steps, rows, ids and columns read
+  // an in-range address), and masked when the stage is stored: a branch on a
+  // loaded value, or a load some paths skip, makes the wait for it cover
+  // every load issued before it, the prefetched rows included.
+  struct Stage {
+    uint4 v[CH];
+    float n, ts;
+    int32_t ti;
+  };
+  Stage st;
+  const int tr = threadIdx.x % TR;  // the tile row whose id, norm and threshold a thread loads
+  auto tile_row = [&](int q) { return C0 + TR * (int64_t)q + tr; };
+  auto load_ids = [&](int q) {
+    const int64_t row = tile_row(q);
+    return (int32_t)order[row < 0 ? 0 : (row >= N ? N - 1 : row)];
+  };
+  auto put_ids = [&](int q, int32_t id) {
+    if (threadIdx.x < TR) {
+      const int64_t row = tile_row(q);
+      tcid[q % 3][tr] = row >= 0 && row < N ? id : -1;
+    }
+  };
+  auto fetch = [&](int q) {
+    const int32_t* ids = tcid[q % 3];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) A[s] = load_row8(Xs, arow, d, 32 * s + 8 * kg);
+    for (int i = 0; i < CH; ++i) {
+      const int x = threadIdx.x + 256 * i;
+      const int rr = (x < TR * CPR ? x : 0) / CPR, k0 = 8 * (x % CPR);
+      const int32_t id = ids[rr];
+      st.v[i] = *(const uint4*)(X + (int64_t)(id < 0 ? 0 : id) * d + (k0 < d ? k0 : 0));
+    }
+    const int32_t id = ids[tr];
+    const int64_t ic = id < 0 ? 0 : id;
+    st.n = nrm[ic];
+    if constexpr (SYM) {
+      st.ti = gids[ic * k + k - 1];
+      st.ts = gsc[ic * k + k - 1];
+    }
+  };
+  auto store = [&](int q) {
+    const int32_t* ids = tcid[q % 3];
+    const int slot = q & 1;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int x = threadIdx.x + 256 * i;
+      const int rr = x / CPR, k0 = 8 * (x % CPR);
+      if (x < TR * CPR) {
+        const bool ok = ids[rr] >= 0 && k0 < d;
+        *(uint4*)(&tile[slot][rr * RS + k0]) = ok ? st.v[i] : make_uint4(0, 0, 0, 0);
+      }
+    }
+    if (threadIdx.x < TR) {
+      const bool ok = ids[threadIdx.x] >= 0;
+      tnrm[slot][threadIdx.x] = ok ? st.n : 1.f;
+      // column threshold: the k-th cosine of the column point's list (any
+      // value it held is a valid lower bound) in dot units over the row norm
+      if constexpr (SYM) tthr[slot][threadIdx.x] = ok && st.ti >= 0 ? margin(st.ts * st.n) : -INFINITY;
+    }
+  };
+
+  // Prologue: ids of the first two steps and the owners' ids, then (one
+  // memory latency later) the owners' lists and mailbox counts and the rows
+  // of the first step, all in flight together.  (Every order has nsteps >= 3.)
+  const int32_t id0 = load_ids(0), id1 = load_ids(1);
   // the owner lane (l < 16) holds the list of row r0 + l
-  TopList<KMAX> L;
   const int64_t own = r0 + l;
   const bool owner = l < 16 && own < N;
   const int64_t own_id = owner ? (int64_t)order[own] : 0;
-  const float own_n = owner ? ns[own] : 1.f;
+  put_ids(0, id0);
+  put_ids(1, id1);
+  half8 A[KS];
+  if constexpr (!SYM) {
+    // with SYM the rows are those of the wavefront's first column block
+    const int64_t arow = r0 + ri < N ? (int64_t)order[r0 + ri] : -1;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) A[s] = load_row8(X, arow, d, 32 * s + 8 * kg);
+  }
+  TopList<KMAX> L;
+  const float own_n = owner ? nrm[own_id] : 1.f;
   L.load(gsc + own_id * k, gids + own_id * k, k, owner);
+  uint32_t nmail = 0;
+  if constexpr (SYM) nmail = owner ? mi.n[own_id] : 0u;
+  block_lds_sync();
+  fetch(0);
+  if constexpr (SYM) {
+    // pairs the point received in the previous order
+    for (uint32_t i = 0; __ballot(i < nmail); ++i) {
+      if (i < nmail) {
+        const uint2 e = mi.e[own_id * w + i];
+        const float cs = __uint_as_float(e.x);
+        const int32_t c = (int32_t)e.y;
+        if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
+      }
+    }
+    if (owner) mi.n[own_id] = 0;
+  }
   // row threshold in dot-product units, lowered by a relative 2^-20 (far
   // beyond the rounding of either side, so a pair below it cannot beat the
   // k-th entry), for the screening test of all lanes; lane (kg, ri) keeps
   // copies for rows 4kg..4kg+3
-  auto margin = [](float x) { return x - fabsf(x) * 0x1p-20f; };
   float wsn = margin(L.ws() * own_n);
   int open = L.wi() < 0;
   float rthr[4], rown[4];
@@ -208,86 +310,48 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
     }
     wave_lds_sync();
   };
-  const int wr = (w + 15) / 16;
-  const int nsteps = (4 + 2 * wr + BPS - 1) / BPS;
-  const int64_t C0 = R0 - 16 * (int64_t)wr;  // first column of block 0
-  // cooperative tile load: chunk x of the tile is row x / CPR, halves 8*(x % CPR).
-  // A tile of whole rows inside the array (d = 32 KS) is one contiguous run
-  // of memory: chunk x is 16-byte vector x from the tile's first row.
-  uint4 stg[CH];
-  int32_t scid = -1;
-  float snrm = 1.f;
-  const bool dense = d == KS * 32;
-  auto fetch = [&](int q) {
-    const int64_t cb0 = C0 + TR * (int64_t)q;
-    if (dense && cb0 >= 0 && cb0 + TR <= N) {
-      const uint4* src = (const uint4*)(Xs + cb0 * d);
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int x = threadIdx.x + 256 * i;
-        stg[i] = make_uint4(0, 0, 0, 0);
-        if ((i + 1) * 256 <= TR * CPR || x < TR * CPR) stg[i] = src[x];
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        const int x = threadIdx.x + 256 * i;
-        const int rr = x / CPR, k0 = 8 * (x % CPR);
-        const int64_t row = cb0 + rr;
-        stg[i] = make_uint4(0, 0, 0, 0);
-        if (x < TR * CPR && row >= 0 && row < N && k0 < d) stg[i] = *(const uint4*)(Xs + row * d + k0);
-      }
-    }
-    scid = -1;
-    snrm = 1.f;
-    if (threadIdx.x < TR) {
-      const int64_t row = cb0 + threadIdx.x;
-      if (row >= 0 && row < N) {
-        scid = (int32_t)order[row];
-        snrm = ns[row];
-      }
-    }
-  };
-  auto store = [&](int slot) {
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int x = threadIdx.x + 256 * i;
-      if (x < TR * CPR) *(uint4*)(&tile[slot][(x / CPR) * RS + 8 * (x % CPR)]) = stg[i];
-    }
-    if (threadIdx.x < TR) {
-      tcid[slot][threadIdx.x] = scid;
-      tnrm[slot][threadIdx.x] = snrm;
-    }
-  };
-  fetch(0);
   store(0);
+
   for (int q = 0; q < nsteps; ++q) {
-    __syncthreads();  // tile q is in slot q & 1; slot (q + 1) & 1 is free
-    if (q + 1 < nsteps) fetch(q + 1);
+    // tile q is in slot q & 1, the ids of steps q and q + 1 are in LDS
+    block_lds_sync();
+    // the ids before the rows, so that the wait for them does not cover the rows
+    const int32_t id2 = load_ids(q + 2 < nsteps ? q + 2 : nsteps - 1);
+    fetch(q + 1 < nsteps ? q + 1 : nsteps - 1);
 #pragma unroll
     for (int hb = 0; hb < BPS; ++hb) {
-    const int blk = BPS * q + hb;
-    const int cb = blk - wv;
-    if (cb >= 0 && cb <= 2 * wr && r0 < N) {
+      const int blk = BPS * q + hb;
+      const int cb = blk - wv;
+      if (cb < 0 || cb > cbmax || r0 >= N) continue;
       const int slot = q & 1;
       const int64_t c0 = C0 + 16 * (int64_t)blk;
-      float4v acc = {0.f, 0.f, 0.f, 0.f};
       const _Float16* bt = &tile[slot][(16 * hb + ri) * RS + 8 * kg];
+      if (SYM && cb == 0) {
+        // the wavefront's own rows, in the MFMA A layout
+#pragma unroll
+        for (int s = 0; s < KS; ++s) A[s] = *(const half8*)(bt + 32 * s);
+      }
+      float4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const half8 B = *(const half8*)(bt + 32 * s);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[s], B, acc, 0, 0, 0);
       }
       // D layout: lane (kg, ri) holds rows 4kg+r (r < 4) of column ri.
-      // Screening in registers against the rows' thresholds; the band and
-      // array bounds are tested per pair only in blocks that cross them.
+      // Screening in registers against the rows' (and with SYM the
+      // columns') thresholds; the band and array bounds are tested per pair
+      // only in blocks that cross them.
       const float cn = tnrm[slot][16 * hb + ri];
       const int64_t o = c0 - r0;  // pair offsets of the block: o - 15 .. o + 15
       const bool inner = c0 >= 0 && c0 + 16 <= N && r0 + 16 <= N &&
-                         ((o >= 16 && o + 15 <= w) || (o <= -16 && o - 15 >= -w));
-      bool pass[4];
+                         ((o >= 16 && o + 15 <= w) || (!SYM && o <= -16 && o - 15 >= -w));
+      bool prow[4], pcol[4];
+      const float ct = SYM ? tthr[slot][16 * hb + ri] : 0.f;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) pass[r] = (ropen[r] != 0) | (acc[r] >= rthr[r] * cn);
+      for (int r = 0; r < 4; ++r) {
+        prow[r] = (ropen[r] != 0) | (acc[r] >= rthr[r] * cn);
+        pcol[r] = SYM && ((ct == -INFINITY) | (acc[r] >= ct * rown[r]));
+      }
       if (!inner) {
         const int off = (int)o + ri;  // column offset from row 0 of the tile
         const bool col_ok = c0 + ri >= 0 && c0 + ri < N;
@@ -295,21 +359,33 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
         for (int r = 0; r < 4; ++r) {
           const int R = 4 * kg + r;
           const int delta = off - R;
-          pass[r] &= col_ok & (r0 + R < N) & (delta != 0) & (delta <= w) & (-delta <= w);
+          const bool in = col_ok & (r0 + R < N) & (delta <= w) &
+                          (SYM ? delta >= 1 : (delta != 0) & (-delta <= w));
+          prow[r] &= in;
+          pcol[r] &= in;
         }
       }
-      if (__ballot(pass[0] | pass[1] | pass[2] | pass[3])) {
-        const int32_t cid = tcid[slot][16 * hb + ri];
+      if (__ballot(prow[0] | prow[1] | prow[2] | prow[3] | pcol[0] | pcol[1] | pcol[2] | pcol[3])) {
+        const int32_t cid = tcid[q % 3][16 * hb + ri];
         bool full = false;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if (pass[r]) {
-            // the exact cosine, as the row's owner would compute it, queued
-            const int R = 4 * kg + r;
-            const uint32_t j = atomicAdd(&qn[wv][R], 1u);
-            qcs[wv][R][j] = acc[r] / (rown[r] * cn);
-            qid[wv][R][j] = cid;
-            full |= j >= (uint32_t)(QCAP - 16);
+          const int32_t rid = __shfl((int32_t)own_id, 4 * kg + r);
+          if (prow[r] | pcol[r]) {
+            // the exact cosine, as the row's owner would compute it
+            const float cs = acc[r] / (rown[r] * cn);
+            if (prow[r]) {
+              const int R = 4 * kg + r;
+              const uint32_t j = atomicAdd(&qn[wv][R], 1u);
+              qcs[wv][R][j] = cs;
+              qid[wv][R][j] = cid;
+              full |= j >= (uint32_t)(QCAP - 16);
+            }
+            if (SYM && pcol[r]) {
+              // a point receives at most w pairs per order: one per position before it
+              const uint32_t j = atomicAdd(&mo.n[cid], 1u);
+              mo.e[(int64_t)cid * w + j] = make_uint2(__float_as_uint(cs), (uint32_t)rid);
+            }
           }
         }
         wave_lds_sync();
@@ -318,24 +394,46 @@ __global__ __launch_bounds__(256) void k_band(const __half* __restrict__ Xs, int
         if (__ballot(full)) drain();
       }
     }
-    }
-    if (q + 1 < nsteps) store((q + 1) & 1);
+    if (q + 1 < nsteps) store(q + 1);
+    if (q + 2 < nsteps) put_ids(q + 2, id2);
   }
   if (r0 < N) drain();
   if (owner) L.save(gsc + own_id * k, gids + own_id * k, k);
+}
+
+// The pairs sent in the last order, merged into every point's list.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_mailbox_final(Mailbox m, int64_t N, int w, int k,
+                                                       int32_t* __restrict__ gids,
+                                                       float* __restrict__ gsc) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= N) return;
+  const uint32_t n = m.n[p];
+  if (n == 0) return;
+  TopList<KMAX> L;
+  L.load(gsc + p * k, gids + p * k, k, true);
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint2 e = m.e[p * w + i];
+    const float cs = __uint_as_float(e.x);
+    const int32_t c = (int32_t)e.y;
+    if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
+  }
+  L.save(gsc + p * k, gids + p * k, k);
+  m.n[p] = 0;
 }
 
 unsigned grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(65536, ceil_div(n, 256)));
 }
 
-template <int KMAX>
+template <int KMAX, bool SYM>
 hf_status launch_band(int ks, const __half* X, int64_t N, int d, const uint32_t* order,
-                      const float* nrm, int w, int k, int32_t* ids, float* sc, hipStream_t s) {
+                      const float* nrm, int w, int k, int32_t* ids, float* sc, Mailbox mi, Mailbox mo,
+                      hipStream_t s) {
   dim3 grid((unsigned)ceil_div(N, 64));
   switch (ks) {
 #define HF_KS(n) \
-  case n: k_band<KMAX, n><<<grid, 256, 0, s>>>(X, N, d, order, nrm, w, k, ids, sc); break;
+  case n: k_band<KMAX, n, SYM><<<grid, 256, 0, s>>>(X, N, d, order, nrm, w, k, ids, sc, mi, mo); break;
     HF_KS(1) HF_KS(2) HF_KS(3) HF_KS(4) HF_KS(5) HF_KS(6) HF_KS(7) HF_KS(8) HF_KS(9) HF_KS(10)
     HF_KS(11) HF_KS(12) HF_KS(13) HF_KS(14) HF_KS(15) HF_KS(16) HF_KS(20) HF_KS(24) HF_KS(32)
 #undef HF_KS
@@ -425,8 +523,8 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     set_error("graph band kernel: d > 1024 not built");
     return HF_ERR_UNSUPPORTED;
   }
-  // A second stream sorts and gathers order t+1 while the band kernel of
-  // order t runs: orders, re-laid rows and norms are double-buffered.
+  // A second stream sorts order t+1 while the band kernel of order t runs:
+  // the orders are double-buffered.
   // (the workspace is declared first so that it is released last, after the
   // guard below has waited for the second stream)
   Workspace ws(s);
@@ -447,13 +545,7 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   uint8_t* codes;
   float* nrm;
   uint32_t* order[2];
-  __half* Xs[2];
-  float* ns[2];
-  for (int b = 0; b < 2; ++b) {
-    HF_TRY(ws.alloc(&Xs[b], (size_t)(N * d)));
-    HF_TRY(ws.alloc(&ns[b], (size_t)N));
-    HF_TRY(ws.alloc(&order[b], (size_t)N));
-  }
+  for (int b = 0; b < 2; ++b) HF_TRY(ws.alloc(&order[b], (size_t)N));
   HF_TRY(ws.alloc(&codes, (size_t)(N * d)));
   HF_TRY(ws.alloc(&nrm, (size_t)N));
   HF_TRY(quantize(X, HF_F16, N * d, e, codes, s));
@@ -465,6 +557,21 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, nrm);
   k_init_lists<<<grid_for(N * p.k), 256, 0, s>>>(ids, scores, N * p.k);
   HF_LAUNCH_CHECK();
+  // Each pair of the band is computed once when the two mailboxes (per point
+  // a count and w entries of 8 bytes) fit in HF_GRAPH_MAILBOX_MIB (default
+  // 32768) MiB; otherwise from both sides.
+  const int w = (int)p.window;
+  int64_t mb_mib = 32768;
+  if (const char* v = getenv("HF_GRAPH_MAILBOX_MIB")) mb_mib = std::max<int64_t>(0, atoll(v));
+  const bool sym = 2 * N * (4 + 8 * (int64_t)w) <= (mb_mib << 20);
+  Mailbox mb[2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  if (sym) {
+    for (int b = 0; b < 2; ++b) {
+      HF_TRY(ws.alloc(&mb[b].n, (size_t)N));
+      HF_TRY(ws.alloc(&mb[b].e, (size_t)N * w));
+      HIP_TRY(hipMemsetAsync(mb[b].n, 0, sizeof(uint32_t) * (size_t)N, s));
+    }
+  }
   const int T = (int)p.n_orders;
   std::vector<int32_t> perm((size_t)T * d);
   std::vector<uint8_t> refl((size_t)T * d);
@@ -477,7 +584,7 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
   HIP_TRY(hipMemcpyAsync(drefl, refl.data(), (size_t)T * d, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(pp.ready, s));
   HIP_TRY(hipStreamWaitEvent(s2, pp.ready, 0));
-  // sort and gather order t into buffer t & 1 on the second stream
+  // sort order t into buffer t & 1 on the second stream
   auto prepare = [&](int t) -> hf_status {
     const int b = t & 1;
     if (t >= 2) HIP_TRY(hipStreamWaitEvent(s2, pp.banded[b], 0));  // band t-2 is done with b
@@ -487,11 +594,6 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
       HF_TRY(hilbert_sort_dev(codes, msb, N, d, dperm + (size_t)t * d, drefl + (size_t)t * d, order[b], nullptr,
                               wt));
     }
-    {
-      StageTimer tg(ST_GGATHER, s2);
-      k_gather_sorted<<<grid_for(N * (d / 8)), 256, 0, s2>>>(X, nrm, order[b], N, d, Xs[b], ns[b]);
-      HF_LAUNCH_CHECK();
-    }
     HIP_TRY(hipEventRecord(pp.sorted[b], s2));
     return HF_OK;
   };
@@ -500,14 +602,30 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     const int b = t & 1;
     HIP_TRY(hipStreamWaitEvent(s, pp.sorted[b], 0));
     {
+      // the band of order t fills mailbox t & 1 and empties the other
       StageTimer tm(ST_GBAND, s);
-      if (p.k <= 16)
-        HF_TRY(launch_band<16>(ks, Xs[b], N, d, order[b], ns[b], (int)p.window, (int)p.k, ids, scores, s));
+      const Mailbox mi = mb[b ^ 1], mo = mb[b];
+      const int k = (int)p.k;
+      hf_status st;
+      if (k <= 16)
+        st = sym ? launch_band<16, true>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s)
+                 : launch_band<16, false>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s);
       else
-        HF_TRY(launch_band<32>(ks, Xs[b], N, d, order[b], ns[b], (int)p.window, (int)p.k, ids, scores, s));
+        st = sym ? launch_band<32, true>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s)
+                 : launch_band<32, false>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s);
+      HF_TRY(st);
     }
     HIP_TRY(hipEventRecord(pp.banded[b], s));
     if (t + 1 < T) HF_TRY(prepare(t + 1));
+  }
+  if (sym) {
+    StageTimer tm(ST_GBAND, s);
+    const Mailbox m = mb[(T - 1) & 1];
+    if (p.k <= 16)
+      k_mailbox_final<16><<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(m, N, w, (int)p.k, ids, scores);
+    else
+      k_mailbox_final<32><<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(m, N, w, (int)p.k, ids, scores);
+    HF_LAUNCH_CHECK();
   }
   HIP_TRY(hipStreamSynchronize(s2));
   HIP_TRY(hipStreamSynchronize(s));

@@ -255,6 +255,23 @@ def test_graph_parity_ragged(hf, orc):
     _graph_case(hf, orc, x, n=2, w=49, k=20, seed=5, rows=np.arange(100))
 
 
+def test_graph_two_sided_band(hf, orc, monkeypatch):
+    """With no room for mailboxes every pair is computed from both of its
+    points; the lists equal the oracle's and, bit for bit, those of the form
+    that computes each pair once."""
+    cases = [(datagen.mixture(333, 40, 4, 0.1, 72, dtype=np.float16), 3, 21, 7, 4),
+             (datagen.mixture(2011, 64, 6, 0.1, 74, dtype=np.float16), 3, 150, 12, 6),
+             (datagen.mixture(5000, 384, 16, 0.05, 75, dtype=np.float16), 2, 128, 15, 7)]
+    once = [hf.knn_graph(dev(x), n, w, k, seed) for x, n, w, k, seed in cases]
+    monkeypatch.setenv("HF_GRAPH_MAILBOX_MIB", "0")
+    for (x, n, w, k, seed), (gi1, gs1) in zip(cases, once):
+        gi2, gs2 = hf.knn_graph(dev(x), n, w, k, seed)
+        assert (gi1.cpu().numpy() == gi2.cpu().numpy()).all()
+        assert (gs1.cpu().numpy() == gs2.cpu().numpy()).all()
+        rows = np.arange(0, x.shape[0], max(1, x.shape[0] // 400))
+        _graph_case(hf, orc, x, n=n, w=w, k=k, seed=seed, rows=rows)
+
+
 def _graph_prefilter_case(hf, orc, x, n, w, k, k2, seed, sk_seed, rows):
     """Sketch stage of Alg. 2: C2 lists bit-exact, results as in the plain form."""
     orders, e = orc.graph_orders(x, n, seed)

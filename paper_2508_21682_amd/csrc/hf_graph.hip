@@ -197,17 +197,23 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
       tcid[q % 3][tr] = row >= 0 && row < N ? id : -1;
     }
   };
+  // Thread t moves tile row t / TPR, chunks t % TPR + TPR j: one id and
+  // one row address per thread, contiguous 16-byte chunks per TPR lanes.
+  // Rows past the array read point 0 and stay unmasked (every pair with
+  // them fails the bounds test); chunks past d are zeroed.
+  constexpr int TPR = 256 / TR;                 // threads per tile row
+  static_assert(TR * TPR == 256 && (CPR + TPR - 1) / TPR == CH, "tile load layout");
+  const int trow = threadIdx.x / TPR, tc = threadIdx.x % TPR;
+  const bool dense = d == 32 * KS;
   auto fetch = [&](int q) {
-    const int32_t* ids = tcid[q % 3];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int x = threadIdx.x + 256 * i;
-      const int rr = (x < TR * CPR ? x : 0) / CPR, k0 = 8 * (x % CPR);
-      const int32_t id = ids[rr];
-      st.v[i] = *(const uint4*)(X + (int64_t)(id < 0 ? 0 : id) * d + (k0 < d ? k0 : 0));
-    }
-    const int32_t id = ids[tr];
+    const int32_t id = tcid[q % 3][trow];
     const int64_t ic = id < 0 ? 0 : id;
+    const __half* src = X + ic * d;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int c = tc + TPR * j;
+      if (c < CPR) st.v[j] = *(const uint4*)(src + (dense || 8 * c < d ? 8 * c : 0));
+    }
     st.n = nrm[ic];
     if constexpr (SYM) {
       st.ti = gids[ic * k + k - 1];
@@ -215,23 +221,23 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
     }
   };
   auto store = [&](int q) {
-    const int32_t* ids = tcid[q % 3];
     const int slot = q & 1;
+    _Float16* dst = &tile[slot][trow * RS];
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int x = threadIdx.x + 256 * i;
-      const int rr = x / CPR, k0 = 8 * (x % CPR);
-      if (x < TR * CPR) {
-        const bool ok = ids[rr] >= 0 && k0 < d;
-        *(uint4*)(&tile[slot][rr * RS + k0]) = ok ? st.v[i] : make_uint4(0, 0, 0, 0);
+    for (int j = 0; j < CH; ++j) {
+      const int c = tc + TPR * j;
+      if (c < CPR) {
+        uint4 v = st.v[j];
+        if (!dense && 8 * c >= d) v = make_uint4(0, 0, 0, 0);
+        *(uint4*)(dst + 8 * c) = v;
       }
     }
-    if (threadIdx.x < TR) {
-      const bool ok = ids[threadIdx.x] >= 0;
-      tnrm[slot][threadIdx.x] = ok ? st.n : 1.f;
+    if (tc == 0) {
+      const bool ok = tcid[q % 3][trow] >= 0;
+      tnrm[slot][trow] = ok ? st.n : 1.f;
       // column threshold: the k-th cosine of the column point's list (any
       // value it held is a valid lower bound) in dot units over the row norm
-      if constexpr (SYM) tthr[slot][threadIdx.x] = ok && st.ti >= 0 ? margin(st.ts * st.n) : -INFINITY;
+      if constexpr (SYM) tthr[slot][trow] = ok && st.ti >= 0 ? margin(st.ts * st.n) : -INFINITY;
     }
   };
 

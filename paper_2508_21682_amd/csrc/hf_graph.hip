@@ -251,9 +251,10 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   const int64_t own_id = owner ? (int64_t)order[own] : 0;
   put_ids(0, id0);
   put_ids(1, id1);
+  // the wavefront's rows, as the MFMA A operand (with SYM taken from the
+  // tile when its first column block, its own rows, arrives)
   half8 A[KS];
   if constexpr (!SYM) {
-    // with SYM the rows are those of the wavefront's first column block
     const int64_t arow = r0 + ri < N ? (int64_t)order[r0 + ri] : -1;
 #pragma unroll
     for (int s = 0; s < KS; ++s) A[s] = load_row8(X, arow, d, 32 * s + 8 * kg);
@@ -333,7 +334,9 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
       const int64_t c0 = C0 + 16 * (int64_t)blk;
       const _Float16* bt = &tile[slot][(16 * hb + ri) * RS + 8 * kg];
       if (SYM && cb == 0) {
-        // the wavefront's own rows, in the MFMA A layout
+        // (the empty asm keeps this a branch: selects on all of A would cost
+        // every block 4 KS instructions)
+        asm volatile("");
 #pragma unroll
         for (int s = 0; s < KS; ++s) A[s] = *(const half8*)(bt + 32 * s);
       }

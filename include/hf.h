@@ -291,7 +291,7 @@ hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash
  * 0 query codes, 1 query sketches, 2 descend, 3 hamming, 4 select, 5 rerank,
  * 6 graph sort, 7 graph band, 8 build sort, 9 build trie, 10 build sketch,
  * 11 lowprec score, 12 graph hamming band, 13 graph list merge, 14 graph
- * final cosine top-k, 15 graph row gather. */
+ * final cosine top-k, 15 graph mailbox merge after the last order. */
 #define HF_N_STAGES 16
 hf_status hf_timing_enable(int32_t on);
 /* Waits for the recorded events, writes the summed milliseconds and launch
@@ -313,7 +313,11 @@ const char* hf_timing_stage_name(int32_t stage);
  * otherwise).  ids_dev: N x k int32 original ids (-1 if fewer candidates);
  * scores_dev: N x k FP32 cosines; both caller-owned.  Synchronises.
  * The sketch stage stages up to 2w keys per position for chunks of positions
- * whose staging fits HF_GRAPH_STAGE_MIB MiB (environment; default 1024). */
+ * whose staging fits HF_GRAPH_STAGE_MIB MiB (environment; default 1024).
+ * Without it, each pair of a window is scored once when two per-point
+ * mailboxes (N (4 + 8w) bytes each) fit HF_GRAPH_MAILBOX_MIB MiB
+ * (environment; default 32768), from both of its points otherwise; the
+ * results are the same. */
 hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
                        const hf_graph_params* params, int32_t* ids_dev, float* scores_dev,
                        void* stream);

@@ -34,7 +34,7 @@ thread_local std::vector<hipEvent_t> t_open(ST_COUNT, nullptr);
 const char* kStageNames[ST_COUNT] = {"query_codes", "query_sketch", "descend", "hamming", "select",
                                      "rerank", "graph_sort", "graph_band", "build_sort", "build_trie",
                                      "build_sketch", "lowprec_score", "graph_hamming", "graph_merge",
-                                     "graph_final", "graph_gather"};
+                                     "graph_final", "graph_mailbox"};
 }  // namespace
 
 bool timing_on() { return t_on; }

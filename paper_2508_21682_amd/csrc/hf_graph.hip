@@ -628,7 +628,7 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     if (t + 1 < T) HF_TRY(prepare(t + 1));
   }
   if (sym) {
-    StageTimer tm(ST_GBAND, s);
+    StageTimer tm(ST_GMAIL, s);
     const Mailbox m = mb[(T - 1) & 1];
     if (p.k <= 16)
       k_mailbox_final<16><<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(m, N, w, (int)p.k, ids, scores);

@@ -213,7 +213,7 @@ hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64
                      uint64_t* out, Workspace& ws);
 // stage timing (hf_api.hip): events around a launch when timing is on
 enum Stage { ST_QCODES = 0, ST_QSKETCH, ST_DESCEND, ST_HAM, ST_SELECT, ST_RERANK, ST_GSORT, ST_GBAND,
-             ST_BSORT, ST_BTRIE, ST_BSKETCH, ST_LOWPREC, ST_GHAM, ST_GMERGE, ST_GFINAL, ST_GGATHER, ST_COUNT };
+             ST_BSORT, ST_BTRIE, ST_BSKETCH, ST_LOWPREC, ST_GHAM, ST_GMERGE, ST_GFINAL, ST_GMAIL, ST_COUNT };
 bool timing_on();
 void timing_mark(int stage, bool begin, hipStream_t s);
 struct StageTimer {

@@ -6,7 +6,9 @@
 // across tiles; (3) each tile ranks its elements stably (wavefront ballots
 // find equal digits inside a 64-element row, per-wave running counters carry
 // the rank across rows and waves), stages them in LDS grouped by digit and
-// writes each digit run out contiguously.
+// writes each digit run out contiguously.  Every global load of a tile is
+// issued before the ranking starts: a load between the ballots would be
+// waited for row by row.
 #include "hf_internal.h"
 
 namespace hf {
@@ -23,13 +25,17 @@ __global__ __launch_bounds__(RS_THREADS) void rs_hist(const uint64_t* __restrict
                                                       int64_t ntiles) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
-  __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * RS_TILE;
-#pragma unroll 4
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  uint32_t dg[RS_ROWS];
+#pragma unroll
   for (int i = 0; i < RS_ROWS; ++i) {
-    int64_t idx = base + (int64_t)i * RS_THREADS + threadIdx.x;
-    if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    const int64_t idx = base + (int64_t)i * RS_THREADS + threadIdx.x;
+    dg[i] = (uint32_t)(keys[idx < n ? idx : n - 1] >> shift) & 255u;
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RS_ROWS; ++i)
+    if (base + (int64_t)i * RS_THREADS + threadIdx.x < n) atomicAdd(&h[dg[i]], 1u);
   __syncthreads();
   counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
@@ -46,19 +52,26 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter(
 
   const int w = threadIdx.x / 64, l = __lane_id();
   const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
-  for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
-  __syncthreads();
-
   uint64_t k[RS_ROWS];
   uint32_t v[RS_ROWS];
   uint32_t rank[RS_ROWS];
+  // the tile's global offset of digit threadIdx.x
+  const uint32_t off = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < RS_ROWS; ++r) {
+    const int64_t idx = tile0 + (int64_t)w * RS_WAVE_SPAN + r * 64 + l;
+    const int64_t ic = idx < n ? idx : n - 1;
+    k[r] = keys[ic];
+    v[r] = vals[ic];
+  }
+  for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_THREADS) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < RS_ROWS; ++r) {
     int64_t idx = tile0 + (int64_t)w * RS_WAVE_SPAN + r * 64 + l;
     bool ok = idx < n;
-    k[r] = ok ? keys[idx] : 0;
-    v[r] = ok ? vals[idx] : 0;
     uint32_t dg = (uint32_t)(k[r] >> shift) & 255u;
     uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -102,12 +115,16 @@ __global__ __launch_bounds__(RS_THREADS) void rs_scatter(
     }
   }
   __syncthreads();
+  // the counters are spent: digit d's output position of LDS slot i is
+  // wcnt[0][d] + i
+  wcnt[0][threadIdx.x] = off - dstart[threadIdx.x];
+  __syncthreads();
   int64_t m = n - tile0;
   if (m > RS_TILE) m = RS_TILE;
   for (int i = threadIdx.x; i < m; i += RS_THREADS) {
     uint64_t kk = skey[i];
     uint32_t dg = (uint32_t)(kk >> shift) & 255u;
-    uint32_t dst = offs[(int64_t)dg * ntiles + blockIdx.x] + (uint32_t)(i - dstart[dg]);
+    uint32_t dst = wcnt[0][dg] + (uint32_t)i;
     okeys[dst] = kk;
     ovals[dst] = sval[i];
   }

@@ -59,6 +59,21 @@ __global__ void k_apply(const uint32_t* __restrict__ o, const uint32_t* __restri
   }
 }
 
+// Round 0: every point is active, in id order, in one segment (A and pts
+// are the identity, seg is 0), so the sorted chunks and ids are the new
+// state as they stand.
+__global__ void k_apply0(const uint32_t* __restrict__ o, const uint64_t* __restrict__ skeys, int64_t n,
+                         uint32_t* __restrict__ order, uint32_t* __restrict__ npts,
+                         uint64_t* __restrict__ nkc, uint32_t* __restrict__ nseg) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    const uint32_t s = o[j];
+    order[j] = s;
+    npts[j] = s;
+    nkc[j] = skeys[j];
+    nseg[j] = 0;
+  }
+}
+
 // tied[j] for the pair (j, j+1): 0 = split (or different segments),
 // 1 = equal chunk, different codes, 2 = equal chunk, identical codes.
 __global__ void k_ties(const uint32_t* __restrict__ npts, const uint64_t* __restrict__ nkc,
@@ -179,7 +194,10 @@ hf_status hilbert_sort_dev(const uint8_t* codes, const uint32_t* msb, int64_t N,
       HF_LAUNCH_CHECK();
       HF_TRY(radix_sort_pairs(&k1, &v1, &k2, &v2, na, 0, (segbits + 7) / 8 * 8, ws));
     }
-    k_apply<<<grid_for(na), 256, 0, s>>>(v1, pts, kc, seg, A, na, order, npts, nkc, nseg);
+    if (c == 0)
+      k_apply0<<<grid_for(na), 256, 0, s>>>(v1, k1, na, order, npts, nkc, nseg);
+    else
+      k_apply<<<grid_for(na), 256, 0, s>>>(v1, pts, kc, seg, A, na, order, npts, nkc, nseg);
     k_ties<<<grid_for(na), 256, 0, s>>>(npts, nkc, nseg, A, na, c, codes, d, scratch_split, tied);
     k_heads<<<grid_for(na), 256, 0, s>>>(tied, na, head);
     HF_LAUNCH_CHECK();

@@ -262,22 +262,18 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   TopList<KMAX> L;
   const float own_n = owner ? nrm[own_id] : 1.f;
   L.load(gsc + own_id * k, gids + own_id * k, k, owner);
+  // The pairs the point received in the previous order are merged after the
+  // last step (the list is the top-k of everything merged into it, whatever
+  // the order; a threshold without them only lets more pairs through): the
+  // count and the first entry are loaded now and used then.
   uint32_t nmail = 0;
-  if constexpr (SYM) nmail = owner ? mi.n[own_id] : 0u;
+  uint2 mail0 = make_uint2(0, 0);
+  if constexpr (SYM) {
+    nmail = mi.n[own_id];
+    mail0 = mi.e[own_id * w];
+  }
   block_lds_sync();
   fetch(0);
-  if constexpr (SYM) {
-    // pairs the point received in the previous order
-    for (uint32_t i = 0; __ballot(i < nmail); ++i) {
-      if (i < nmail) {
-        const uint2 e = mi.e[own_id * w + i];
-        const float cs = __uint_as_float(e.x);
-        const int32_t c = (int32_t)e.y;
-        if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
-      }
-    }
-    if (owner) mi.n[own_id] = 0;
-  }
   // row threshold in dot-product units, lowered by a relative 2^-20 (far
   // beyond the rounding of either side, so a pair below it cannot beat the
   // k-th entry), for the screening test of all lanes; lane (kg, ri) keeps
@@ -407,6 +403,18 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
     if (q + 2 < nsteps) put_ids(q + 2, id2);
   }
   if (r0 < N) drain();
+  if constexpr (SYM) {
+    const uint32_t n = owner ? nmail : 0u;
+    for (uint32_t i = 0; __ballot(i < n); ++i) {
+      if (i < n) {
+        const uint2 e = i == 0 ? mail0 : mi.e[own_id * w + i];
+        const float cs = __uint_as_float(e.x);
+        const int32_t c = (int32_t)e.y;
+        if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
+      }
+    }
+    if (owner) mi.n[own_id] = 0;
+  }
   if (owner) L.save(gsc + own_id * k, gids + own_id * k, k);
 }
 

@@ -27,7 +27,11 @@ namespace {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
-__global__ void k_norms(const __half* __restrict__ X, int64_t N, int d, float* __restrict__ nrm) {
+// Row norms into nrm[p * stride]; with stride 2 the second word of each pair
+// (the band kernel's point record: norm, k-th cosine of the point's list) is
+// set to -inf, the mark of a list not yet full.
+__global__ void k_norms(const __half* __restrict__ X, int64_t N, int d, float* __restrict__ nrm,
+                        int stride = 1) {
   int64_t p = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (p >= N) return;
   float a = 0.f;
@@ -36,7 +40,10 @@ __global__ void k_norms(const __half* __restrict__ X, int64_t N, int d, float* _
     a = fmaf(v, v, a);
   }
   for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m);
-  if (__lane_id() == 0) nrm[p] = sqrtf(a);
+  if (__lane_id() == 0) {
+    nrm[p * stride] = sqrtf(a);
+    if (stride == 2) nrm[p * 2 + 1] = -INFINITY;
+  }
 }
 
 __global__ void k_init_lists(int32_t* __restrict__ ids, float* __restrict__ sc, int64_t n) {
@@ -139,7 +146,7 @@ struct Mailbox {
 template <int KMAX, int KS, bool SYM>
 __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(const __half* __restrict__ X, int64_t N, int d,
                                               const uint32_t* __restrict__ order,
-                                              const float* __restrict__ nrm, int w, int k,
+                                              float2* __restrict__ pt, int w, int k,
                                               int32_t* __restrict__ gids, float* __restrict__ gsc,
                                               Mailbox mi, Mailbox mo) {
   constexpr int BPS = 2;           // column blocks per step
@@ -182,7 +189,6 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   struct Stage {
     uint4 v[CH];
     float n, ts;
-    int32_t ti;
   };
   Stage st;
   const int tr = threadIdx.x % TR;  // the tile row whose id, norm and threshold a thread loads
@@ -214,11 +220,9 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
       const int c = tc + TPR * j;
       if (c < CPR) st.v[j] = *(const uint4*)(src + (dense || 8 * c < d ? 8 * c : 0));
     }
-    st.n = nrm[ic];
-    if constexpr (SYM) {
-      st.ti = gids[ic * k + k - 1];
-      st.ts = gsc[ic * k + k - 1];
-    }
+    const float2 rec = pt[ic];
+    st.n = rec.x;
+    st.ts = rec.y;
   };
   auto store = [&](int q) {
     const int slot = q & 1;
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
       tnrm[slot][trow] = ok ? st.n : 1.f;
       // column threshold: the k-th cosine of the column point's list (any
       // value it held is a valid lower bound) in dot units over the row norm
-      if constexpr (SYM) tthr[slot][trow] = ok && st.ti >= 0 ? margin(st.ts * st.n) : -INFINITY;
+      if constexpr (SYM) tthr[slot][trow] = ok && st.ts != -INFINITY ? margin(st.ts * st.n) : -INFINITY;
     }
   };
 
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
     for (int s = 0; s < KS; ++s) A[s] = load_row8(X, arow, d, 32 * s + 8 * kg);
   }
   TopList<KMAX> L;
-  const float own_n = owner ? nrm[own_id] : 1.f;
+  const float own_n = owner ? pt[own_id].x : 1.f;
   L.load(gsc + own_id * k, gids + own_id * k, k, owner);
   // The pairs the point received in the previous order are merged after the
   // last step (the list is the top-k of everything merged into it, whatever
@@ -415,7 +419,10 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
     }
     if (owner) mi.n[own_id] = 0;
   }
-  if (owner) L.save(gsc + own_id * k, gids + own_id * k, k);
+  if (owner) {
+    L.save(gsc + own_id * k, gids + own_id * k, k);
+    pt[own_id].y = L.ws();  // -inf while the list is not full
+  }
 }
 
 // The pairs sent in the last order, merged into every point's list.
@@ -445,12 +452,12 @@ unsigned grid_for(int64_t n) {
 
 template <int KMAX, bool SYM>
 hf_status launch_band(int ks, const __half* X, int64_t N, int d, const uint32_t* order,
-                      const float* nrm, int w, int k, int32_t* ids, float* sc, Mailbox mi, Mailbox mo,
+                      float2* pt, int w, int k, int32_t* ids, float* sc, Mailbox mi, Mailbox mo,
                       hipStream_t s) {
   dim3 grid((unsigned)ceil_div(N, 64));
   switch (ks) {
 #define HF_KS(n) \
-  case n: k_band<KMAX, n, SYM><<<grid, 256, 0, s>>>(X, N, d, order, nrm, w, k, ids, sc, mi, mo); break;
+  case n: k_band<KMAX, n, SYM><<<grid, 256, 0, s>>>(X, N, d, order, pt, w, k, ids, sc, mi, mo); break;
     HF_KS(1) HF_KS(2) HF_KS(3) HF_KS(4) HF_KS(5) HF_KS(6) HF_KS(7) HF_KS(8) HF_KS(9) HF_KS(10)
     HF_KS(11) HF_KS(12) HF_KS(13) HF_KS(14) HF_KS(15) HF_KS(16) HF_KS(20) HF_KS(24) HF_KS(32)
 #undef HF_KS
@@ -560,18 +567,18 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   hipStream_t s2 = pp.s2;
   uint8_t* codes;
-  float* nrm;
+  float2* pt;  // per point: norm, k-th cosine of its list (-inf until full)
   uint32_t* order[2];
   for (int b = 0; b < 2; ++b) HF_TRY(ws.alloc(&order[b], (size_t)N));
   HF_TRY(ws.alloc(&codes, (size_t)(N * d)));
-  HF_TRY(ws.alloc(&nrm, (size_t)N));
+  HF_TRY(ws.alloc(&pt, (size_t)N));
   HF_TRY(quantize(X, HF_F16, N * d, e, codes, s));
   uint32_t* msb = nullptr;
   if (msb_words(d) > 0) {
     HF_TRY(ws.alloc(&msb, (size_t)(N * msb_words(d))));
     HF_TRY(msb_plane(codes, N, d, msb, s));
   }
-  k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, nrm);
+  k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, (float*)pt, 2);
   k_init_lists<<<grid_for(N * p.k), 256, 0, s>>>(ids, scores, N * p.k);
   HF_LAUNCH_CHECK();
   // Each pair of the band is computed once when the two mailboxes (per point
@@ -625,11 +632,11 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
       const int k = (int)p.k;
       hf_status st;
       if (k <= 16)
-        st = sym ? launch_band<16, true>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s)
-                 : launch_band<16, false>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s);
+        st = sym ? launch_band<16, true>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s)
+                 : launch_band<16, false>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s);
       else
-        st = sym ? launch_band<32, true>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s)
-                 : launch_band<32, false>(ks, X, N, d, order[b], nrm, w, k, ids, scores, mi, mo, s);
+        st = sym ? launch_band<32, true>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s)
+                 : launch_band<32, false>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s);
       HF_TRY(st);
     }
     HIP_TRY(hipEventRecord(pp.banded[b], s));

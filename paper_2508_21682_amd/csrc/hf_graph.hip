@@ -46,10 +46,26 @@ __global__ void k_norms(const __half* __restrict__ X, int64_t N, int d, float* _
   }
 }
 
-__global__ void k_init_lists(int32_t* __restrict__ ids, float* __restrict__ sc, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    ids[i] = -1;
-    sc[i] = -INFINITY;
+// The band kernel's working lists: per point the KMAX (cosine, id) slots of
+// its top-k list as a TopList holds them (KMAX - k sentinels, then the k
+// entries, the k-th in the last slot), 8 bytes a slot: one 128-byte line a
+// point at KMAX = 16.
+__global__ void k_init_slots(uint2* __restrict__ slots, int64_t n, int kmax, int k) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n * kmax; i += (int64_t)gridDim.x * 256) {
+    const bool sentinel = (int)(i % kmax) < kmax - k;
+    slots[i] = sentinel ? make_uint2(__float_as_uint(INFINITY), (uint32_t)-2)
+                        : make_uint2(__float_as_uint(-INFINITY), (uint32_t)-1);
+  }
+}
+
+// The lists out of the working slots: ids (-1 where fewer than k) and cosines.
+__global__ void k_slots_out(const uint2* __restrict__ slots, int64_t n, int kmax, int k,
+                            int32_t* __restrict__ ids, float* __restrict__ sc) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n * k; i += (int64_t)gridDim.x * 256) {
+    const int64_t p = i / k;
+    const uint2 e = slots[p * kmax + kmax - k + (i - p * k)];
+    sc[i] = __uint_as_float(e.x);
+    ids[i] = (int32_t)e.y;
   }
 }
 
@@ -78,6 +94,23 @@ struct TopList {
         li[i] = id[e];
       }
     }
+  }
+  // whole slot arrays (sentinels included), 16-byte vectors of two slots
+  __device__ __forceinline__ void load_slots(const uint4* src) {
+#pragma unroll
+    for (int j = 0; j < KMAX / 2; ++j) {
+      const uint4 v = src[j];
+      ls[2 * j] = __uint_as_float(v.x);
+      li[2 * j] = (int32_t)v.y;
+      ls[2 * j + 1] = __uint_as_float(v.z);
+      li[2 * j + 1] = (int32_t)v.w;
+    }
+  }
+  __device__ __forceinline__ void save_slots(uint4* dst) const {
+#pragma unroll
+    for (int j = 0; j < KMAX / 2; ++j)
+      dst[j] = make_uint4(__float_as_uint(ls[2 * j]), (uint32_t)li[2 * j], __float_as_uint(ls[2 * j + 1]),
+                          (uint32_t)li[2 * j + 1]);
   }
   __device__ __forceinline__ void save(float* sc, int32_t* id, int k) const {
 #pragma unroll
@@ -147,8 +180,7 @@ template <int KMAX, int KS, bool SYM>
 __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(const __half* __restrict__ X, int64_t N, int d,
                                               const uint32_t* __restrict__ order,
                                               float2* __restrict__ pt, int w, int k,
-                                              int32_t* __restrict__ gids, float* __restrict__ gsc,
-                                              Mailbox mi, Mailbox mo) {
+                                              uint4* __restrict__ slots, Mailbox mi, Mailbox mo) {
   constexpr int BPS = 2;           // column blocks per step
   constexpr int TR = 16 * BPS;     // tile rows
   constexpr int RS = KS * 32 + 8;  // LDS row stride (halves)
@@ -265,7 +297,10 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   }
   TopList<KMAX> L;
   const float own_n = owner ? pt[own_id].x : 1.f;
-  L.load(gsc + own_id * k, gids + own_id * k, k, owner);
+  if (owner)
+    L.load_slots(slots + own_id * (KMAX / 2));
+  else
+    L.load(nullptr, nullptr, k, false);
   // The pairs the point received in the previous order are merged after the
   // last step (the list is the top-k of everything merged into it, whatever
   // the order; a threshold without them only lets more pairs through): the
@@ -420,29 +455,28 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
     if (owner) mi.n[own_id] = 0;
   }
   if (owner) {
-    L.save(gsc + own_id * k, gids + own_id * k, k);
+    L.save_slots(slots + own_id * (KMAX / 2));
     pt[own_id].y = L.ws();  // -inf while the list is not full
   }
 }
 
 // The pairs sent in the last order, merged into every point's list.
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_mailbox_final(Mailbox m, int64_t N, int w, int k,
-                                                       int32_t* __restrict__ gids,
-                                                       float* __restrict__ gsc) {
+__global__ __launch_bounds__(256) void k_mailbox_final(Mailbox m, int64_t N, int w,
+                                                       uint4* __restrict__ slots) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= N) return;
   const uint32_t n = m.n[p];
   if (n == 0) return;
   TopList<KMAX> L;
-  L.load(gsc + p * k, gids + p * k, k, true);
+  L.load_slots(slots + p * (KMAX / 2));
   for (uint32_t i = 0; i < n; ++i) {
     const uint2 e = m.e[p * w + i];
     const float cs = __uint_as_float(e.x);
     const int32_t c = (int32_t)e.y;
     if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
   }
-  L.save(gsc + p * k, gids + p * k, k);
+  L.save_slots(slots + p * (KMAX / 2));
   m.n[p] = 0;
 }
 
@@ -452,12 +486,11 @@ unsigned grid_for(int64_t n) {
 
 template <int KMAX, bool SYM>
 hf_status launch_band(int ks, const __half* X, int64_t N, int d, const uint32_t* order,
-                      float2* pt, int w, int k, int32_t* ids, float* sc, Mailbox mi, Mailbox mo,
-                      hipStream_t s) {
+                      float2* pt, int w, int k, uint4* slots, Mailbox mi, Mailbox mo, hipStream_t s) {
   dim3 grid((unsigned)ceil_div(N, 64));
   switch (ks) {
 #define HF_KS(n) \
-  case n: k_band<KMAX, n, SYM><<<grid, 256, 0, s>>>(X, N, d, order, pt, w, k, ids, sc, mi, mo); break;
+  case n: k_band<KMAX, n, SYM><<<grid, 256, 0, s>>>(X, N, d, order, pt, w, k, slots, mi, mo); break;
     HF_KS(1) HF_KS(2) HF_KS(3) HF_KS(4) HF_KS(5) HF_KS(6) HF_KS(7) HF_KS(8) HF_KS(9) HF_KS(10)
     HF_KS(11) HF_KS(12) HF_KS(13) HF_KS(14) HF_KS(15) HF_KS(16) HF_KS(20) HF_KS(24) HF_KS(32)
 #undef HF_KS
@@ -579,7 +612,10 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     HF_TRY(msb_plane(codes, N, d, msb, s));
   }
   k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, (float*)pt, 2);
-  k_init_lists<<<grid_for(N * p.k), 256, 0, s>>>(ids, scores, N * p.k);
+  const int kmax = p.k <= 16 ? 16 : 32;
+  uint4* slots;
+  HF_TRY(ws.alloc(&slots, (size_t)N * kmax / 2));
+  k_init_slots<<<grid_for(N * kmax), 256, 0, s>>>((uint2*)slots, N, kmax, (int)p.k);
   HF_LAUNCH_CHECK();
   // Each pair of the band is computed once when the two mailboxes (per point
   // a count and w entries of 8 bytes) fit in HF_GRAPH_MAILBOX_MIB (default
@@ -632,23 +668,27 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
       const int k = (int)p.k;
       hf_status st;
       if (k <= 16)
-        st = sym ? launch_band<16, true>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s)
-                 : launch_band<16, false>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s);
+        st = sym ? launch_band<16, true>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s)
+                 : launch_band<16, false>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s);
       else
-        st = sym ? launch_band<32, true>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s)
-                 : launch_band<32, false>(ks, X, N, d, order[b], pt, w, k, ids, scores, mi, mo, s);
+        st = sym ? launch_band<32, true>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s)
+                 : launch_band<32, false>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s);
       HF_TRY(st);
     }
     HIP_TRY(hipEventRecord(pp.banded[b], s));
     if (t + 1 < T) HF_TRY(prepare(t + 1));
   }
-  if (sym) {
+  {
+    // the last order's mailboxes, then the lists out of the working slots
     StageTimer tm(ST_GMAIL, s);
-    const Mailbox m = mb[(T - 1) & 1];
-    if (p.k <= 16)
-      k_mailbox_final<16><<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(m, N, w, (int)p.k, ids, scores);
-    else
-      k_mailbox_final<32><<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(m, N, w, (int)p.k, ids, scores);
+    if (sym) {
+      const Mailbox m = mb[(T - 1) & 1];
+      if (p.k <= 16)
+        k_mailbox_final<16><<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(m, N, w, slots);
+      else
+        k_mailbox_final<32><<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(m, N, w, slots);
+    }
+    k_slots_out<<<grid_for(N * p.k), 256, 0, s>>>((const uint2*)slots, N, kmax, (int)p.k, ids, scores);
     HF_LAUNCH_CHECK();
   }
   HIP_TRY(hipStreamSynchronize(s2));

@@ -315,7 +315,7 @@ const char* hf_timing_stage_name(int32_t stage);
  * The sketch stage stages up to 2w keys per position for chunks of positions
  * whose staging fits HF_GRAPH_STAGE_MIB MiB (environment; default 1024).
  * Without it, each pair of a window is scored once when two per-point
- * mailboxes (N (4 + 8w) bytes each) fit HF_GRAPH_MAILBOX_MIB MiB
+ * mailboxes (8 N w bytes each) fit HF_GRAPH_MAILBOX_MIB MiB
  * (environment; default 32768), from both of its points otherwise; the
  * results are the same. */
 hf_status hf_knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,

@@ -27,9 +27,10 @@ namespace {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
-// Row norms into nrm[p * stride]; with stride 2 the second word of each pair
-// (the band kernel's point record: norm, k-th cosine of the point's list) is
-// set to -inf, the mark of a list not yet full.
+// Row norms into nrm[p * stride].  With stride 4 the rest of each record
+// (the band kernel's point record: norm, k-th cosine of the point's list,
+// the counts of its two mailboxes) is set to -inf (the mark of a list not
+// yet full) and two zero counts.
 __global__ void k_norms(const __half* __restrict__ X, int64_t N, int d, float* __restrict__ nrm,
                         int stride = 1) {
   int64_t p = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
@@ -41,8 +42,10 @@ __global__ void k_norms(const __half* __restrict__ X, int64_t N, int d, float* _
   }
   for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m);
   if (__lane_id() == 0) {
-    nrm[p * stride] = sqrtf(a);
-    if (stride == 2) nrm[p * 2 + 1] = -INFINITY;
+    if (stride == 4)
+      ((float4*)nrm)[p] = make_float4(sqrtf(a), -INFINITY, 0.f, 0.f);
+    else
+      nrm[p * stride] = sqrtf(a);
   }
 }
 
@@ -153,8 +156,8 @@ __device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t
 }
 
 // Pairs sent to a point by the band kernel of one order, for its owner to
-// merge in the next order: per point a count and up to w (cosine, id)
-// entries.
+// merge in the next order: per point a count (point p's at n[4 p], a word of
+// its record) and up to w (cosine, id) entries.
 struct Mailbox {
   uint32_t* n;
   uint2* e;
@@ -179,7 +182,7 @@ struct Mailbox {
 template <int KMAX, int KS, bool SYM>
 __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(const __half* __restrict__ X, int64_t N, int d,
                                               const uint32_t* __restrict__ order,
-                                              float2* __restrict__ pt, int w, int k,
+                                              float4* __restrict__ pt, int w, int k,
                                               uint4* __restrict__ slots, Mailbox mi, Mailbox mo) {
   constexpr int BPS = 2;           // column blocks per step
   constexpr int TR = 16 * BPS;     // tile rows
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
       const int c = tc + TPR * j;
       if (c < CPR) st.v[j] = *(const uint4*)(src + (dense || 8 * c < d ? 8 * c : 0));
     }
-    const float2 rec = pt[ic];
+    const float2 rec = *(const float2*)&pt[ic];
     st.n = rec.x;
     st.ts = rec.y;
   };
@@ -296,7 +299,7 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
     for (int s = 0; s < KS; ++s) A[s] = load_row8(X, arow, d, 32 * s + 8 * kg);
   }
   TopList<KMAX> L;
-  const float own_n = owner ? pt[own_id].x : 1.f;
+  const float own_n = owner ? pt[own_id].x : 1.f;  // (the record's line also holds the mail count)
   if (owner)
     L.load_slots(slots + own_id * (KMAX / 2));
   else
@@ -304,13 +307,9 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   // The pairs the point received in the previous order are merged after the
   // last step (the list is the top-k of everything merged into it, whatever
   // the order; a threshold without them only lets more pairs through): the
-  // count and the first entry are loaded now and used then.
+  // count is loaded now and used then.
   uint32_t nmail = 0;
-  uint2 mail0 = make_uint2(0, 0);
-  if constexpr (SYM) {
-    nmail = mi.n[own_id];
-    mail0 = mi.e[own_id * w];
-  }
+  if constexpr (SYM) nmail = mi.n[own_id * 4];
   block_lds_sync();
   fetch(0);
   // row threshold in dot-product units, lowered by a relative 2^-20 (far
@@ -427,7 +426,7 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
             }
             if (SYM && pcol[r]) {
               // a point receives at most w pairs per order: one per position before it
-              const uint32_t j = atomicAdd(&mo.n[cid], 1u);
+              const uint32_t j = atomicAdd(&mo.n[(int64_t)cid * 4], 1u);
               mo.e[(int64_t)cid * w + j] = make_uint2(__float_as_uint(cs), (uint32_t)rid);
             }
           }
@@ -446,13 +445,13 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
     const uint32_t n = owner ? nmail : 0u;
     for (uint32_t i = 0; __ballot(i < n); ++i) {
       if (i < n) {
-        const uint2 e = i == 0 ? mail0 : mi.e[own_id * w + i];
+        const uint2 e = mi.e[own_id * w + i];
         const float cs = __uint_as_float(e.x);
         const int32_t c = (int32_t)e.y;
         if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
       }
     }
-    if (owner) mi.n[own_id] = 0;
+    if (owner) mi.n[own_id * 4] = 0;
   }
   if (owner) {
     L.save_slots(slots + own_id * (KMAX / 2));
@@ -466,7 +465,7 @@ __global__ __launch_bounds__(256) void k_mailbox_final(Mailbox m, int64_t N, int
                                                        uint4* __restrict__ slots) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= N) return;
-  const uint32_t n = m.n[p];
+  const uint32_t n = m.n[p * 4];
   if (n == 0) return;
   TopList<KMAX> L;
   L.load_slots(slots + p * (KMAX / 2));
@@ -477,7 +476,7 @@ __global__ __launch_bounds__(256) void k_mailbox_final(Mailbox m, int64_t N, int
     if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
   }
   L.save_slots(slots + p * (KMAX / 2));
-  m.n[p] = 0;
+  m.n[p * 4] = 0;
 }
 
 unsigned grid_for(int64_t n) {
@@ -486,7 +485,7 @@ unsigned grid_for(int64_t n) {
 
 template <int KMAX, bool SYM>
 hf_status launch_band(int ks, const __half* X, int64_t N, int d, const uint32_t* order,
-                      float2* pt, int w, int k, uint4* slots, Mailbox mi, Mailbox mo, hipStream_t s) {
+                      float4* pt, int w, int k, uint4* slots, Mailbox mi, Mailbox mo, hipStream_t s) {
   dim3 grid((unsigned)ceil_div(N, 64));
   switch (ks) {
 #define HF_KS(n) \
@@ -600,7 +599,7 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   hipStream_t s2 = pp.s2;
   uint8_t* codes;
-  float2* pt;  // per point: norm, k-th cosine of its list (-inf until full)
+  float4* pt;  // per point: norm, k-th cosine of its list (-inf until full), two mail counts
   uint32_t* order[2];
   for (int b = 0; b < 2; ++b) HF_TRY(ws.alloc(&order[b], (size_t)N));
   HF_TRY(ws.alloc(&codes, (size_t)(N * d)));
@@ -611,25 +610,24 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
     HF_TRY(ws.alloc(&msb, (size_t)(N * msb_words(d))));
     HF_TRY(msb_plane(codes, N, d, msb, s));
   }
-  k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, (float*)pt, 2);
+  k_norms<<<(unsigned)ceil_div(N, 4), 256, 0, s>>>(X, N, d, (float*)pt, 4);
   const int kmax = p.k <= 16 ? 16 : 32;
   uint4* slots;
   HF_TRY(ws.alloc(&slots, (size_t)N * kmax / 2));
   k_init_slots<<<grid_for(N * kmax), 256, 0, s>>>((uint2*)slots, N, kmax, (int)p.k);
   HF_LAUNCH_CHECK();
   // Each pair of the band is computed once when the two mailboxes (per point
-  // a count and w entries of 8 bytes) fit in HF_GRAPH_MAILBOX_MIB (default
-  // 32768) MiB; otherwise from both sides.
+  // w entries of 8 bytes; the counts are words of the point records) fit in
+  // HF_GRAPH_MAILBOX_MIB (default 32768) MiB; otherwise from both sides.
   const int w = (int)p.window;
   int64_t mb_mib = 32768;
   if (const char* v = getenv("HF_GRAPH_MAILBOX_MIB")) mb_mib = std::max<int64_t>(0, atoll(v));
-  const bool sym = 2 * N * (4 + 8 * (int64_t)w) <= (mb_mib << 20);
+  const bool sym = 2 * N * 8 * (int64_t)w <= (mb_mib << 20);
   Mailbox mb[2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   if (sym) {
     for (int b = 0; b < 2; ++b) {
-      HF_TRY(ws.alloc(&mb[b].n, (size_t)N));
+      mb[b].n = (uint32_t*)pt + 2 + b;  // zeroed with the records
       HF_TRY(ws.alloc(&mb[b].e, (size_t)N * w));
-      HIP_TRY(hipMemsetAsync(mb[b].n, 0, sizeof(uint32_t) * (size_t)N, s));
     }
   }
   const int T = (int)p.n_orders;

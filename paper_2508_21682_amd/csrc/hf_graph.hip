@@ -149,6 +149,70 @@ struct TopList {
   }
 };
 
+// The top-k list of one row spread over four lanes of a wavefront: lane
+// R + 16 j holds slots SPL j .. SPL j + SPL - 1 of row R, in the slot layout
+// of TopList (KMAX - k sentinels first, the k-th entry in the last slot).
+// The four lanes of a row insert together: each counts the slots of its own
+// that stay ahead of the candidate, two xor-shuffles give the position, and
+// every slot past it takes its predecessor (the first slot of a lane takes
+// the last of the lane before).
+template <int KMAX>
+struct RowList {
+  static constexpr int SPL = KMAX / 4;
+  float ls[SPL];
+  int32_t li[SPL];
+  __device__ __forceinline__ void init(int k, int j) {
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+      const bool sentinel = SPL * j + q < KMAX - k;
+      ls[q] = sentinel ? INFINITY : -INFINITY;
+      li[q] = sentinel ? -2 : -1;
+    }
+  }
+  // `row`: the point's KMAX / 2 16-byte vectors of slots
+  __device__ __forceinline__ void load(const uint4* row, int j) {
+#pragma unroll
+    for (int v = 0; v < SPL / 2; ++v) {
+      const uint4 x = row[j * (SPL / 2) + v];
+      ls[2 * v] = __uint_as_float(x.x);
+      li[2 * v] = (int32_t)x.y;
+      ls[2 * v + 1] = __uint_as_float(x.z);
+      li[2 * v + 1] = (int32_t)x.w;
+    }
+  }
+  __device__ __forceinline__ void save(uint4* row, int j) const {
+#pragma unroll
+    for (int v = 0; v < SPL / 2; ++v)
+      row[j * (SPL / 2) + v] = make_uint4(__float_as_uint(ls[2 * v]), (uint32_t)li[2 * v],
+                                          __float_as_uint(ls[2 * v + 1]), (uint32_t)li[2 * v + 1]);
+  }
+  // called by the four lanes of the row together, with the same (s, c)
+  __device__ __forceinline__ void insert(float s, int32_t c, int j) {
+    int dup = 0, ahead = 0;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+      dup |= li[q] == c;
+      ahead += li[q] != -1 && !better(s, c, ls[q], li[q]);
+    }
+    dup |= __shfl_xor(dup, 16);
+    dup |= __shfl_xor(dup, 32);
+    ahead += __shfl_xor(ahead, 16);
+    ahead += __shfl_xor(ahead, 32);
+    const int src = (__lane_id() + 48) & 63;  // the row's lane before this one
+    const float ps = __shfl(ls[SPL - 1], src);
+    const int32_t pi = __shfl(li[SPL - 1], src);
+    if (dup || ahead >= KMAX) return;
+#pragma unroll
+    for (int q = SPL - 1; q >= 0; --q) {
+      const int g = SPL * j + q;
+      const float os = q > 0 ? ls[q - 1] : ps;
+      const int32_t oi = q > 0 ? li[q - 1] : pi;
+      ls[q] = g > ahead ? os : (g == ahead ? s : ls[q]);
+      li[q] = g > ahead ? oi : (g == ahead ? c : li[q]);
+    }
+  }
+};
+
 __device__ __forceinline__ half8 load_row8(const __half* __restrict__ X, int64_t r, int d, int k0) {
   if (r < 0 || k0 >= d) return (half8)(0);
   uint4 raw = *(const uint4*)(X + r * d + k0);
@@ -298,12 +362,16 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
 #pragma unroll
     for (int s = 0; s < KS; ++s) A[s] = load_row8(X, arow, d, 32 * s + 8 * kg);
   }
-  TopList<KMAX> L;
   const float own_n = owner ? pt[own_id].x : 1.f;  // (the record's line also holds the mail count)
-  if (owner)
-    L.load_slots(slots + own_id * (KMAX / 2));
+  // row ri's list, over lanes ri + 16 j (j = kg)
+  const bool row_ok = r0 + ri < N;
+  const int64_t row_id = __shfl((int32_t)own_id, ri);
+  const float row_n = __shfl(own_n, ri);
+  RowList<KMAX> L;
+  if (row_ok)
+    L.load(slots + row_id * (KMAX / 2), kg);
   else
-    L.load(nullptr, nullptr, k, false);
+    L.init(k, kg);
   // The pairs the point received in the previous order are merged after the
   // last step (the list is the top-k of everything merged into it, whatever
   // the order; a threshold without them only lets more pairs through): the
@@ -315,15 +383,17 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   // row threshold in dot-product units, lowered by a relative 2^-20 (far
   // beyond the rounding of either side, so a pair below it cannot beat the
   // k-th entry), for the screening test of all lanes; lane (kg, ri) keeps
-  // copies for rows 4kg..4kg+3
-  float wsn = margin(L.ws() * own_n);
-  int open = L.wi() < 0;
+  // copies for rows 4kg..4kg+3.  The k-th entry of row R is the last slot
+  // of lane R + 48.
+  constexpr int SPL = RowList<KMAX>::SPL;
+  float wsn = margin(L.ls[SPL - 1] * row_n);
+  int open = L.li[SPL - 1] < 0;
   float rthr[4], rown[4];
   int ropen[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    rthr[r] = __shfl(wsn, 4 * kg + r);
-    ropen[r] = __shfl(open, 4 * kg + r);
+    rthr[r] = __shfl(wsn, 48 + 4 * kg + r);
+    ropen[r] = __shfl(open, 48 + 4 * kg + r);
     rown[r] = __shfl(own_n, 4 * kg + r);
   }
   // Pairs that pass the screening wait in a per-row queue; the owners merge
@@ -333,21 +403,18 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   if (l < 16) qn[wv][l] = 0;
   wave_lds_sync();
   auto drain = [&]() {
-    const uint32_t n = owner ? qn[wv][l] : 0u;
-    for (uint32_t i = 0; __ballot(i < n); ++i) {
-      if (i < n) {
-        const float cs = qcs[wv][l][i];
-        const int32_t c = qid[wv][l][i];
-        if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
-      }
-    }
+    // the four lanes of row ri take its queue entries together
+    const uint32_t n = row_ok ? qn[wv][ri] : 0u;
+    for (uint32_t i = 0; __ballot(i < n); ++i)
+      if (i < n) L.insert(qcs[wv][ri][i], qid[wv][ri][i], kg);
+    wave_lds_sync();
     if (l < 16) qn[wv][l] = 0;
-    wsn = margin(L.ws() * own_n);
-    open = L.wi() < 0;
+    wsn = margin(L.ls[SPL - 1] * row_n);
+    open = L.li[SPL - 1] < 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      rthr[r] = __shfl(wsn, 4 * kg + r);
-      ropen[r] = __shfl(open, 4 * kg + r);
+      rthr[r] = __shfl(wsn, 48 + 4 * kg + r);
+      ropen[r] = __shfl(open, 48 + 4 * kg + r);
     }
     wave_lds_sync();
   };
@@ -442,21 +509,18 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
   }
   if (r0 < N) drain();
   if constexpr (SYM) {
-    const uint32_t n = owner ? nmail : 0u;
+    const uint32_t n = row_ok ? (uint32_t)__shfl((int32_t)nmail, ri) : 0u;
     for (uint32_t i = 0; __ballot(i < n); ++i) {
       if (i < n) {
-        const uint2 e = mi.e[own_id * w + i];
-        const float cs = __uint_as_float(e.x);
-        const int32_t c = (int32_t)e.y;
-        if (L.wi() < 0 || better(cs, c, L.ws(), L.wi())) L.insert(cs, c);
+        const uint2 e = mi.e[row_id * w + i];
+        L.insert(__uint_as_float(e.x), (int32_t)e.y, kg);
       }
     }
     if (owner) mi.n[own_id * 4] = 0;
   }
-  if (owner) {
-    L.save_slots(slots + own_id * (KMAX / 2));
-    pt[own_id].y = L.ws();  // -inf while the list is not full
-  }
+  if (row_ok) L.save(slots + row_id * (KMAX / 2), kg);
+  const float kth = __shfl(L.ls[SPL - 1], 48 + (l & 15));
+  if (owner) pt[own_id].y = kth;  // -inf while the list is not full
 }
 
 // The pairs sent in the last order, merged into every point's list.

@@ -410,8 +410,8 @@ def main():
     ap.add_argument("--k1", type=int, default=150)
     ap.add_argument("--k2", type=int, default=800)
     ap.add_argument("--h", type=int, default=8)
-    ap.add_argument("--orders", type=int, default=264)
-    ap.add_argument("--window", type=int, default=128)
+    ap.add_argument("--orders", type=int, default=232)
+    ap.add_argument("--window", type=int, default=160)
     ap.add_argument("--sweep", default=None,
                     help="extra configs: search 'k1,k2,h;...', graph 'orders,w[,k2];...'")
     ap.add_argument("--forms", default="bf16,fp8", help="precision forms measured after the plain search")

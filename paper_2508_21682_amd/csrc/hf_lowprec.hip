@@ -154,16 +154,24 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
     const uint32_t p = ok ? epos(st, off, n2, e) : 0u;
     // FP8: the row's scale, fetched with its codes (lane l holds row l % 16)
     float rs = 1.f;
-    if constexpr (PREC == 2) rs = ok ? s8[p] : 1.f;
+    if constexpr (PREC == 2) rs = s8[p];  // (position 0 when past E: never used)
     float4v acc = {0.f, 0.f, 0.f, 0.f};
+    // Row loads are unconditional (rows past E read position 0 and their
+    // scores are not stored; chunks past d are zeroed after the load): a
+    // load some lanes skip would be waited for chunk by chunk.
     if constexpr (PREC == 1) {
       const uint16_t* row = (const uint16_t*)Xlp + (int64_t)p * d;
+      uint4 a[KS];
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int k0 = 32 * s + 8 * g;
-        uint4 a = (ok && k0 < d) ? *(const uint4*)(row + k0) : make_uint4(0, 0, 0, 0);
+        a[s] = *(const uint4*)(row + (k0 < d ? k0 : 0));
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        if (32 * s + 8 * g >= d) a[s] = make_uint4(0, 0, 0, 0);
         uint4 b = make_uint4(qb[s][0], qb[s][1], qb[s][2], qb[s][3]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[s]),
                                                       __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
       }
     } else {
@@ -171,8 +179,10 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int k0 = 128 * s + 32 * g;
-        uint4 a0 = (ok && k0 < d) ? *(const uint4*)(row + k0) : make_uint4(0, 0, 0, 0);
-        uint4 a1 = (ok && k0 + 16 < d) ? *(const uint4*)(row + k0 + 16) : make_uint4(0, 0, 0, 0);
+        uint4 a0 = *(const uint4*)(row + (k0 < d ? k0 : 0));
+        uint4 a1 = *(const uint4*)(row + (k0 + 16 < d ? k0 + 16 : 0));
+        if (k0 >= d) a0 = make_uint4(0, 0, 0, 0);
+        if (k0 + 16 >= d) a1 = make_uint4(0, 0, 0, 0);
         int8v A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
         int8v B = {(int)qb[s][0], (int)qb[s][1], (int)qb[s][2], (int)qb[s][3],
                    (int)qb[s][4], (int)qb[s][5], (int)qb[s][6], (int)qb[s][7]};

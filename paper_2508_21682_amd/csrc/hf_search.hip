@@ -52,6 +52,9 @@ __global__ __launch_bounds__(256) void k_descend(const uint32_t* __restrict__ no
 // ---------------------------------------------------------------- ham + hist
 constexpr int HB = 513;  // Hamming values 0..512
 
+// U groups of 64 window entries per pass: the launch takes ceil(len / 64),
+// at most 4, so short windows load no idle group.
+template <int U>
 __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_perm, int64_t N,
                                              int T, int len, int64_t qstride,
                                              const uint32_t* __restrict__ win,
@@ -69,24 +72,26 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
   for (int t = 0; t < T; ++t) {
     const uint32_t* P = tree_perm + (int64_t)t * N + win[q * T + t];
     uint16_t* o = out + (int64_t)t * len;
-    for (int i0 = 0; i0 < len; i0 += 4 * 64) {
-      uint32_t pos[4];
-      ulonglong2 v[4];
+    for (int i0 = 0; i0 < len; i0 += U * 64) {
+      // all position loads, then all sketch loads, unconditional (entries
+      // past the window read its last one and are not used): a load some
+      // lanes skip would be waited for one by one
+      uint32_t pos[U];
+      ulonglong2 v[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int i = i0 + u * 64 + grp;
-        pos[u] = i < len ? P[i] : 0u;
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * 64 + grp;
+        pos[u] = P[i < len ? i : len - 1];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        int i = i0 + u * 64 + grp;
-        if (i < len) v[u] = *(const ulonglong2*)(sk + (int64_t)pos[u] * 8 + 2 * qd);
-      }
+      for (int u = 0; u < U; ++u) v[u] = *(const ulonglong2*)(sk + (int64_t)pos[u] * 8 + 2 * qd);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
         int i = i0 + u * 64 + grp;
-        uint32_t c = 0;
-        if (i < len) c = (uint32_t)(__popcll(v[u].x ^ q0) + __popcll(v[u].y ^ q1));
+        // computed for every entry and masked (a use under `i < len` would
+        // let the compiler sink the load into that branch)
+        uint32_t c = (uint32_t)(__popcll(v[u].x ^ q0) + __popcll(v[u].y ^ q1));
+        c = i < len ? c : 0u;
         c += __shfl_xor(c, 1);
         c += __shfl_xor(c, 2);
         if (i < len && qd == 0) {
@@ -539,8 +544,10 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     const int64_t nb = std::min(batch, nq - q0);
     {
       StageTimer tm(ST_HAM, s);
-      k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, per_q, win + q0 * T, f->sk_pos,
-                                         qsk + q0 * 8, ham, hist);
+      const int U = (int)std::min<int64_t>(4, ceil_div(len, 64));
+      auto kh = U == 1 ? k_ham<1> : U == 2 ? k_ham<2> : U == 3 ? k_ham<3> : k_ham<4>;
+      kh<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, per_q, win + q0 * T, f->sk_pos, qsk + q0 * 8,
+                                      ham, hist);
       HF_LAUNCH_CHECK();
     }
     {

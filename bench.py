@@ -407,9 +407,9 @@ def main():
     ap.add_argument("--trees", type=int, default=720)
     ap.add_argument("--leaf", type=int, default=100)
     ap.add_argument("--k", type=int, default=None)
-    ap.add_argument("--k1", type=int, default=150)
-    ap.add_argument("--k2", type=int, default=800)
-    ap.add_argument("--h", type=int, default=8)
+    ap.add_argument("--k1", type=int, default=165)
+    ap.add_argument("--k2", type=int, default=710)
+    ap.add_argument("--h", type=int, default=7)
     ap.add_argument("--orders", type=int, default=232)
     ap.add_argument("--window", type=int, default=160)
     ap.add_argument("--sweep", default=None,

@@ -728,13 +728,18 @@ hf_status graph_launch(const void* Xv, hf_dtype dt, int64_t N, int d, const hf_g
       StageTimer tm(ST_GBAND, s);
       const Mailbox mi = mb[b ^ 1], mo = mb[b];
       const int k = (int)p.k;
+      // The first two orders score every pair from both sides: nearly every
+      // pair passes against lists still empty or weak, and two-sided
+      // pushes go to the LDS queues instead of returning global atomics on
+      // the mailboxes.  (Order 2 finds order 1's mailbox empty.)
+      const bool sym_t = sym && t >= 2;
       hf_status st;
       if (k <= 16)
-        st = sym ? launch_band<16, true>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s)
-                 : launch_band<16, false>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s);
+        st = sym_t ? launch_band<16, true>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s)
+                   : launch_band<16, false>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s);
       else
-        st = sym ? launch_band<32, true>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s)
-                 : launch_band<32, false>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s);
+        st = sym_t ? launch_band<32, true>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s)
+                   : launch_band<32, false>(ks, X, N, d, order[b], pt, w, k, slots, mi, mo, s);
       HF_TRY(st);
     }
     HIP_TRY(hipEventRecord(pp.banded[b], s));

@@ -10,6 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhf.so")
+PEAKS_SRC = os.path.join(HERE, "peaks", "peaks.hip")
+PEAKS = os.path.join(HERE, "peaks", "hf_peaks")
 ARCH = os.environ.get("HF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -23,15 +25,26 @@ def sources():
 
 
 def _compile(src):
+    if src is None:
+        return build_peaks()
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     subprocess.check_call([HIPCC] + FLAGS + ["-c", src, "-o", obj])
     return obj
 
 
+def build_peaks() -> str:
+    """The standalone ceiling probes (copy, random gathers, fp16 MFMA) that
+    `bench.py --peaks` runs; not part of libhf."""
+    tmp = PEAKS + ".tmp%d" % os.getpid()
+    subprocess.check_call([HIPCC] + [f for f in FLAGS if f != "-fPIC"] + [PEAKS_SRC, "-o", tmp])
+    os.replace(tmp, PEAKS)
+    return PEAKS
+
+
 def build(jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, sources()))
+        objs = list(ex.map(_compile, sources() + [None]))[:-1]
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp])
     os.replace(tmp, LIB)

@@ -52,55 +52,81 @@ __global__ __launch_bounds__(256) void k_descend(const uint32_t* __restrict__ no
 // ---------------------------------------------------------------- ham + hist
 constexpr int HB = 513;  // Hamming values 0..512
 
-// U groups of 64 window entries per pass: the launch takes ceil(len / 64),
-// at most 4, so short windows load no idle group.
-template <int U>
+// The n*len window entries of one query form one list, entry e = t*len + i
+// (tree t, offset i in its window), taken 256 at a time: the group of four
+// lanes grp reads the sketches of entries e0 + 4 grp + u, u < 4, 16 bytes a
+// lane.  Lane qd of the group loads the position of entry e0 + 4 grp + qd
+// (the group shares them by quad broadcasts) and ends with that entry's
+// distance, so a wave stores 64 consecutive distances at once.  Positions of
+// the next 256 entries are loaded while the current sketches are in flight.
+// No load or store is conditional (entries past the list read its last
+// position and write into the row's padding, which is a multiple of 256
+// entries; their histogram count goes to a spare bin): a memory operation
+// that some paths skip makes the compiler wait for every one before it.
+// mlen = ceil(2^32 / len): t = (e * mlen) >> 32 is floor(e / len) or one
+// more, since e < 2^30.
+// quad_perm DPP moves: lane i of each quad reads lane sel[i] of the quad
+template <int CTRL>
+__device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t v, int u) {
+  return u == 0 ? quad_perm<0x00>(v) : u == 1 ? quad_perm<0x55>(v) : u == 2 ? quad_perm<0xAA>(v) : quad_perm<0xFF>(v);
+}
+constexpr int QP_XOR1 = 0xB1;  // [1, 0, 3, 2]
+constexpr int QP_XOR2 = 0x4E;  // [2, 3, 0, 1]
+
 __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_perm, int64_t N,
-                                             int T, int len, int64_t qstride,
+                                             int T, int len, uint64_t mlen, int64_t qstride,
                                              const uint32_t* __restrict__ win,
                                              const uint64_t* __restrict__ sk,
                                              const uint64_t* __restrict__ qsk,
                                              uint16_t* __restrict__ ham,
                                              uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[4][HB];
+  __shared__ uint32_t h[4][HB + 1];
+  __shared__ uint32_t s_win[1024];
   const int64_t q = blockIdx.x;
-  for (int i = threadIdx.x; i < 4 * HB; i += 256) (&h[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < 4 * (HB + 1); i += 256) (&h[0][0])[i] = 0;
+  for (int t = threadIdx.x; t < T; t += 256) s_win[t] = win[q * T + t];
   __syncthreads();
   const int w = threadIdx.x / 64, grp = threadIdx.x / 4, qd = threadIdx.x & 3;
   const uint64_t q0 = qsk[q * 8 + 2 * qd], q1 = qsk[q * 8 + 2 * qd + 1];
   uint16_t* out = ham + q * qstride;
-  for (int t = 0; t < T; ++t) {
-    const uint32_t* P = tree_perm + (int64_t)t * N + win[q * T + t];
-    uint16_t* o = out + (int64_t)t * len;
-    for (int i0 = 0; i0 < len; i0 += U * 64) {
-      // all position loads, then all sketch loads, unconditional (entries
-      // past the window read its last one and are not used): a load some
-      // lanes skip would be waited for one by one
-      uint32_t pos[U];
-      ulonglong2 v[U];
+  const uint32_t total = (uint32_t)T * (uint32_t)len, ulen = (uint32_t)len;
+  auto pos_of = [&](uint32_t e) -> uint32_t {
+    e = e < total ? e : total - 1u;
+    uint32_t t = (uint32_t)(((uint64_t)e * mlen) >> 32);
+    t -= t * ulen > e ? 1u : 0u;
+    return tree_perm[(int64_t)t * N + s_win[t] + (e - t * ulen)];
+  };
+  const uint32_t mine = (uint32_t)(4 * grp + qd);
+  const bool b0 = qd & 1, b1 = qd & 2;
+  uint32_t pc = pos_of(mine);
+  __builtin_amdgcn_sched_barrier(0);
+  // a store behind the first position load, as every iteration has one behind
+  // its position load (the first iteration overwrites it): the wait for the
+  // position then never has to include the store
+  out[mine] = 0;
+  uint32_t e0 = 0;
+  do {  // total >= 1
+    ulonglong2 v[4];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * 64 + grp;
-        pos[u] = P[i < len ? i : len - 1];
-      }
+    for (int u = 0; u < 4; ++u) v[u] = *(const ulonglong2*)(sk + (int64_t)quad_bcast(pc, u) * 8 + 2 * qd);
+    pc = pos_of(e0 + 256u + mine);
+    // issue the next position load before any use of the sketches
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t a[4];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = *(const ulonglong2*)(sk + (int64_t)pos[u] * 8 + 2 * qd);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        int i = i0 + u * 64 + grp;
-        // computed for every entry and masked (a use under `i < len` would
-        // let the compiler sink the load into that branch)
-        uint32_t c = (uint32_t)(__popcll(v[u].x ^ q0) + __popcll(v[u].y ^ q1));
-        c = i < len ? c : 0u;
-        c += __shfl_xor(c, 1);
-        c += __shfl_xor(c, 2);
-        if (i < len && qd == 0) {
-          o[i] = (uint16_t)c;
-          atomicAdd(&h[w][c], 1u);
-        }
-      }
-    }
-  }
+    for (int u = 0; u < 4; ++u) a[u] = (uint32_t)(__popcll(v[u].x ^ q0) + __popcll(v[u].y ^ q1));
+    // reduce-scatter over the quad: lane qd ends with the sum for entry u = qd
+    const uint32_t k0 = (b0 ? a[1] : a[0]) + quad_perm<QP_XOR1>(b0 ? a[0] : a[1]);  // u = b0
+    const uint32_t k1 = (b0 ? a[3] : a[2]) + quad_perm<QP_XOR1>(b0 ? a[2] : a[3]);  // u = 2 + b0
+    const uint32_t c = (b1 ? k1 : k0) + quad_perm<QP_XOR2>(b1 ? k0 : k1);
+    const uint32_t e = e0 + mine;
+    out[e] = (uint16_t)c;
+    atomicAdd(&h[w][e < total ? c : (uint32_t)HB], 1u);
+    e0 += 256;
+  } while (e0 < total);
   __syncthreads();
   for (int i = threadIdx.x; i < HB; i += 256)
     hist[q * HB + i] = h[0][i] + h[1][i] + h[2][i] + h[3][i];
@@ -486,7 +512,7 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     HF_LAUNCH_CHECK();
   }
   // the second stage runs in batches of queries sized to bound scratch memory
-  const int64_t per_q = ((int64_t)T * len + 7) / 8 * 8;  // 16-byte aligned rows of distances
+  const int64_t per_q = ((int64_t)T * len + 255) / 256 * 256;  // rows of distances padded to 256 entries
   int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1ll << 31) / (per_q * 2 + 1)));
   batch = ceil_div(nq, ceil_div(nq, batch));  // equal batches
   uint16_t* ham;
@@ -544,10 +570,9 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     const int64_t nb = std::min(batch, nq - q0);
     {
       StageTimer tm(ST_HAM, s);
-      const int U = (int)std::min<int64_t>(4, ceil_div(len, 64));
-      auto kh = U == 1 ? k_ham<1> : U == 2 ? k_ham<2> : U == 3 ? k_ham<3> : k_ham<4>;
-      kh<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, per_q, win + q0 * T, f->sk_pos, qsk + q0 * 8,
-                                      ham, hist);
+      const uint64_t mlen = ((1ull << 32) + (uint64_t)len - 1) / (uint64_t)len;
+      k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, mlen, per_q, win + q0 * T, f->sk_pos,
+                                         qsk + q0 * 8, ham, hist);
       HF_LAUNCH_CHECK();
     }
     {

@@ -65,7 +65,7 @@ typedef struct hf_lhash hf_lhash;
  * about M points).  struct_size must be sizeof(hf_forest_params). */
 typedef struct hf_forest_params {
   uint32_t struct_size;
-  uint32_t n_trees;      /* n, 1..1024; tree 0's order is the master order */
+  uint32_t n_trees;      /* n, 1..4096 (4N bytes of HBM each); tree 0's order is the master order */
   uint32_t leaf_max;     /* M >= 1: ranges of at most M points become leaves */
   int32_t quant_exp;     /* code exponent e, or HF_QUANT_AUTO (from the data) */
   uint64_t seed;         /* seeds the curves (axis permutation + reflection) */

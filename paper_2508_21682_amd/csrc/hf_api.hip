@@ -293,7 +293,7 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   HF_ARG(valid_dtype(dtype), "bad dtype");
   HF_ARG(N >= 1 && N < (1ll << 31), "N must be in [1, 2^31)");
   HF_ARG(d >= 1 && d <= 4096, "d must be in [1, 4096]");
-  HF_ARG(params->n_trees >= 1 && params->n_trees <= 1024, "n_trees must be in [1, 1024]");
+  HF_ARG(params->n_trees >= 1 && params->n_trees <= 4096, "n_trees must be in [1, 4096]");
   HF_ARG(params->leaf_max >= 1, "leaf_max must be >= 1");
   HF_ARG(params->quant_exp == HF_QUANT_AUTO || (params->quant_exp >= -8 && params->quant_exp <= 24),
          "quant_exp must be HF_QUANT_AUTO or in [-8, 24]");

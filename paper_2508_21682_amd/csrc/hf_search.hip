@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
                                              uint16_t* __restrict__ ham,
                                              uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[4][HB + 1];
-  __shared__ uint32_t s_win[1024];
+  extern __shared__ uint32_t s_win[];  // T window starts (dynamic LDS)
   const int64_t q = blockIdx.x;
   for (int i = threadIdx.x; i < 4 * (HB + 1); i += 256) (&h[0][0])[i] = 0;
   for (int t = threadIdx.x; t < T; t += 256) s_win[t] = win[q * T + t];
@@ -571,8 +571,9 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     {
       StageTimer tm(ST_HAM, s);
       const uint64_t mlen = ((1ull << 32) + (uint64_t)len - 1) / (uint64_t)len;
-      k_ham<<<(unsigned)nb, 256, 0, s>>>(f->tree_perm, N, T, len, mlen, per_q, win + q0 * T, f->sk_pos,
-                                         qsk + q0 * 8, ham, hist);
+      k_ham<<<(unsigned)nb, 256, sizeof(uint32_t) * (size_t)T, s>>>(f->tree_perm, N, T, len, mlen, per_q,
+                                                                   win + q0 * T, f->sk_pos, qsk + q0 * 8, ham,
+                                                                   hist);
       HF_LAUNCH_CHECK();
     }
     {

@@ -206,6 +206,13 @@ def test_forest_search_large_candidate_sets(hf, orc):
     _forest_case(hf, orc, x, q, T=16, M=100, seed=13, sk_seed=14, params=[(2500, 600, 2, 20), (2048, 300, 0, 10)])
 
 
+def test_forest_search_many_trees(hf, orc):
+    """1,100 trees: more window starts per query than 1,024 (the Hamming
+    filter keeps them in LDS sized by the tree count)."""
+    x, q = datagen.mixture(2000, 8, 6, 0.1, 71, unit=False, dtype=np.float32, query_seed=72, nq=24)
+    _forest_case(hf, orc, x, q, T=1100, M=20, seed=3, sk_seed=4, params=[(6, 40, 1, 5), (37, 200, 0, 10)])
+
+
 def test_forest_duplicates_overflow_selection(hf, orc):
     """All points identical: one oversized leaf, every candidate at Hamming 0,
     more candidates than the selection buffer holds (position-split path)."""

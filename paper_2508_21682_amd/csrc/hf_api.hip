@@ -141,7 +141,7 @@ hf_status data_exp(const void* X, hf_dtype dt, int64_t n, int32_t want, int* e, 
 void forest_release(hf_forest* f) {
   if (!f) return;
   void* ptrs[] = {f->X_pos, f->sk_pos, f->pos2id, f->tree_perm, f->nodes, f->curve_perm, f->curve_refl,
-                  f->X_bf16, f->X_fp8, f->s_fp8};
+                  f->X_bf16, f->X_fp8, f->s_fp8, f->node_off_dev, f->srp_R};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   f->magic = 0;
@@ -387,6 +387,9 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   f->node_off.assign(T + 1, 0);
   for (int t = 0; t < T; ++t) f->node_off[t + 1] = f->node_off[t] + tcount[t];
   HIP_TRY(hipMalloc(&f->nodes, sizeof(uint32_t) * 2 * (size_t)f->node_off[T]));
+  HIP_TRY(hipMalloc(&f->node_off_dev, sizeof(int64_t) * (size_t)(T + 1)));
+  HIP_TRY(hipMemcpyAsync(f->node_off_dev, f->node_off.data(), sizeof(int64_t) * (size_t)(T + 1),
+                         hipMemcpyHostToDevice, s));
   for (int t = 0; t < T; ++t)
     HIP_TRY(hipMemcpyAsync(f->nodes + 2 * f->node_off[t], tnodes[t], 8 * (size_t)tcount[t],
                            hipMemcpyDeviceToDevice, s));
@@ -394,13 +397,15 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
                                                                (int64_t)(esz * d), f->pos2id, N,
                                                                (unsigned char*)f->X_pos);
   HF_LAUNCH_CHECK();
+  size_t r_bytes = 0;
+  HF_TRY(srp_matrix_upload(d, params->sketch_seed, &f->srp_R, &r_bytes, s));
   {
     StageTimer tm(ST_BSKETCH, s);
-    HF_TRY(srp_sketch(f->X_pos, dtype, N, d, e, params->sketch_seed, f->sk_pos, ws));
+    HF_TRY(srp_sketch(f->X_pos, dtype, N, d, e, params->sketch_seed, f->sk_pos, ws, f->srp_R));
   }
   HIP_TRY(hipStreamSynchronize(s));
   f->device_bytes = (int64_t)(esz * N * d + 64 * N + 4 * N + 4 * (size_t)T * N +
-                              8 * (size_t)f->node_off[T] + 5 * (size_t)T * d);
+                              8 * (size_t)f->node_off[T] + 5 * (size_t)T * d + 8 * (size_t)(T + 1) + r_bytes);
   guard.f = nullptr;
   *out = f;
   return HF_OK;
@@ -524,7 +529,7 @@ hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash
     HF_TRY(lhash_encode_dev(lhash, f->X_pos, f->dtype, f->N, f->sk_pos, s));
   } else {
     Workspace ws(s);
-    HF_TRY(srp_sketch(f->X_pos, f->dtype, f->N, f->d, f->e, f->sketch_seed, f->sk_pos, ws));
+    HF_TRY(srp_sketch(f->X_pos, f->dtype, f->N, f->d, f->e, f->sketch_seed, f->sk_pos, ws, f->srp_R));
   }
   HIP_TRY(hipStreamSynchronize(s));
   f->sketch_kind = (int)kind;

@@ -209,8 +209,12 @@ hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_
                      const uint8_t* refl, const uint32_t* order, const uint32_t* split,
                      uint32_t** nodes_out, int64_t* n_nodes, Workspace& ws);
 // hf_sketch.hip
+// SRP sketches of N rows; R_dev: a resident projection matrix (a forest's),
+// else it is generated from sketch_seed, uploaded and waited for
 hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64_t sketch_seed,
-                     uint64_t* out, Workspace& ws);
+                     uint64_t* out, Workspace& ws, const uint64_t* R_dev = nullptr);
+// the projection matrix of (d, sketch_seed) in a new device buffer (hipMalloc)
+hf_status srp_matrix_upload(int d, uint64_t sketch_seed, uint64_t** out, size_t* bytes, hipStream_t s);
 // stage timing (hf_api.hip): events around a launch when timing is on
 enum Stage { ST_QCODES = 0, ST_QSKETCH, ST_DESCEND, ST_HAM, ST_SELECT, ST_RERANK, ST_GSORT, ST_GBAND,
              ST_BSORT, ST_BTRIE, ST_BSKETCH, ST_LOWPREC, ST_GHAM, ST_GMERGE, ST_GFINAL, ST_GMAIL, ST_COUNT };
@@ -263,6 +267,8 @@ struct hf_forest {
   uint32_t* tree_perm;   // T x N master positions
   uint32_t* nodes;       // all trees' records, 2 words per node
   std::vector<int64_t> node_off;  // T+1 offsets (in nodes)
+  int64_t* node_off_dev; // the same offsets on the device
+  uint64_t* srp_R;       // SRP projection matrix of (d, sketch_seed) on the device
   int32_t* curve_perm;   // T x d
   uint8_t* curve_refl;   // T x d
   void* X_bf16;          // N x d bfloat16 copy of X_pos (precision form), or null

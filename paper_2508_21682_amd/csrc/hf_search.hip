@@ -498,13 +498,11 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     if (f->sketch_kind == HF_SKETCH_LEARNED)
       HF_TRY(lhash_encode_dev(f->lhash, Q, f->dtype, nq, qsk, s));
     else
-      HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws));
+      HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws, f->srp_R));
   }
   uint32_t* win = win_out;
   if (!win) HF_TRY(ws.alloc(&win, (size_t)(nq * T)));
-  int64_t* doff;
-  HF_TRY(ws.alloc(&doff, (size_t)(T + 1)));
-  HIP_TRY(hipMemcpyAsync(doff, f->node_off.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, s));
+  const int64_t* doff = f->node_off_dev;
   {
     dim3 grid((unsigned)ceil_div(nq, 256), (unsigned)T);
     StageTimer tm(ST_DESCEND, s);

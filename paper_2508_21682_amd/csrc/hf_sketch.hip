@@ -79,15 +79,34 @@ static std::vector<uint64_t> srp_matrix(int d, uint64_t sketch_seed) {
   return Rt;
 }
 
+hf_status srp_matrix_upload(int d, uint64_t sketch_seed, uint64_t** out, size_t* bytes, hipStream_t s) {
+  std::vector<uint64_t> Rt = srp_matrix(d, sketch_seed);
+  HIP_TRY(hipMalloc(out, Rt.size() * 8));
+  HIP_TRY(hipMemcpyAsync(*out, Rt.data(), Rt.size() * 8, hipMemcpyHostToDevice, s));
+  // the host copy must outlive the async upload
+  HIP_TRY(hipStreamSynchronize(s));
+  *bytes = Rt.size() * 8;
+  return HF_OK;
+}
+
 hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64_t sketch_seed,
-                     uint64_t* out, Workspace& ws) {
+                     uint64_t* out, Workspace& ws, const uint64_t* R_dev) {
   if (N <= 0) return HF_OK;
+  float scale = ldexpf(1.0f, e + 5);
+  unsigned grid = (unsigned)ceil_div(N, SK_PTS);
+  if (R_dev) {
+    // the matrix is resident (a forest's): nothing to generate, upload or wait for
+    if (dt == HF_F16)
+      srp_kernel<__half><<<grid, 256, 0, ws.stream>>>((const __half*)X, N, d, scale, R_dev, out);
+    else
+      srp_kernel<float><<<grid, 256, 0, ws.stream>>>((const float*)X, N, d, scale, R_dev, out);
+    HF_LAUNCH_CHECK();
+    return HF_OK;
+  }
   std::vector<uint64_t> Rt = srp_matrix(d, sketch_seed);
   uint64_t* dRt;
   HF_TRY(ws.alloc(&dRt, Rt.size()));
   HIP_TRY(hipMemcpyAsync(dRt, Rt.data(), Rt.size() * 8, hipMemcpyHostToDevice, ws.stream));
-  float scale = ldexpf(1.0f, e + 5);
-  unsigned grid = (unsigned)ceil_div(N, SK_PTS);
   if (dt == HF_F16)
     srp_kernel<__half><<<grid, 256, 0, ws.stream>>>((const __half*)X, N, d, scale, dRt, out);
   else

@@ -220,12 +220,15 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
           hf = h;
           break;
         }
-      // bins from hf on until they hold `need` entries plus a margin for
-      // duplicates (few: windows of different trees rarely overlap), or CAP
+      // bins from hf on until they hold twice `need` entries (plus 64), or
+      // CAP: the entries of smallest distance are the query's near
+      // neighbours, which sit in the windows of many trees, so duplicates
+      // are common there; a round short of `need` distinct entries would
+      // cost two more scans of the query's row (histogram, collection)
       int hb = -1;
       if (hf >= 0) {
         uint32_t cum = 0;
-        const uint32_t enough = (uint32_t)need + (uint32_t)need / 8u + 64u;
+        const uint32_t enough = 2u * (uint32_t)need + 64u;
         for (int h = hf; h < HB && h - hf < HM; ++h) {
           if (cum + hist[h] > (uint32_t)CAP) break;
           cum += hist[h];

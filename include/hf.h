@@ -286,6 +286,31 @@ hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash
 
 /* ------------------------------------------------------------------ timing */
 
+/* Scratch allocator.  Every call takes its per-call scratch (device memory
+ * beyond its inputs and outputs: query codes and sketches, window starts,
+ * distances, candidate lists, sort and graph workspaces) on its stream and
+ * gives it back, stream-ordered, once its work is enqueued.  By default that
+ * is hipMallocAsync / hipFreeAsync on the device's default memory pool.  A
+ * caller with its own device allocator (a framework's caching allocator, a
+ * preallocated arena) registers it here:
+ *   alloc(bytes, ctx, stream) returns device memory that work enqueued on
+ *     `stream` after the call may use, or NULL (the call then fails with
+ *     HF_ERR_OOM);
+ *   free(ptr, ctx, stream) takes it back after the call has enqueued all of
+ *     its work on `stream` (the memory may be reused by later work on that
+ *     stream, in stream order).
+ * a == NULL restores the default.  The setting is process-wide; change it
+ * only while no call is in flight (a call keeps the allocator it started
+ * with).  Long-lived storage (forests, learned hashes, precision copies)
+ * stays on hipMalloc.  This is the interface of the caller-owned
+ * allocator in the boundary of the search and graph calls. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx, void* stream);
+  void (*free)(void* ptr, void* ctx, void* stream);
+  void* ctx;
+} hf_allocator;
+hf_status hf_set_allocator(const hf_allocator* a);
+
 /* Per-kernel timing with hipEvents recorded on the caller's stream around
  * each launch of the hot kernels (thread-local; off by default).  Stages:
  * 0 query codes, 1 query sketches, 2 descend, 3 hamming, 4 select, 5 rerank,

@@ -31,7 +31,7 @@ EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_qu
            "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name", "hf_forest_add_precision",
            "hf_search_lowprec_debug", "hf_audit_scores", "hf_lhash_create", "hf_lhash_free", "hf_lhash_get",
            "hf_lhash_encode", "hf_lhash_grad", "hf_lhash_train", "hf_forest_set_sketch",
-           "hf_knn_graph_debug"]
+           "hf_knn_graph_debug", "hf_set_allocator"]
 N_STAGES = 16
 
 
@@ -136,12 +136,14 @@ def lib():
             "hf_lhash_train": (C.c_int, [P, P, P, C.c_int, i64, i32, P, P, P]),
             "hf_forest_set_sketch": (C.c_int, [P, C.c_int, P, P]),
             "hf_knn_graph_debug": (C.c_int, [P, C.c_int, i64, i32, P, P, P, P, P]),
+            "hf_set_allocator": (C.c_int, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
         _lib = L
+        restore_default_allocator()
     return _lib
 
 
@@ -223,6 +225,51 @@ def srp_sketch(x, e: int, sketch_seed: int):
     out = _empty((N, 8), _torch().int64, x)
     _check(lib().hf_srp_sketch(_ptr(x), _dtype(x), N, d, e, sketch_seed, _ptr(out), _stream()))
     return out
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """hf_allocator: the library's per-call scratch goes through these callbacks."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+def _torch_alloc(nbytes, ctx, stream):
+    try:
+        return _torch().cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # reported by the library as HF_ERR_OOM
+        return None
+
+
+def _torch_free(ptr, ctx, stream):
+    _torch().cuda.caching_allocator_delete(int(ptr))
+
+
+_allocator = None  # keeps the registered callbacks alive
+
+
+def restore_default_allocator():
+    """The binding's default: per-call scratch from torch's caching allocator
+    (a search at 23M x 384 takes about 2 GB of scratch per call, which the
+    cache hands back without a new device mapping each time)."""
+    use_torch_allocator(True)
+
+
+def use_torch_allocator(on: bool = True):
+    """Route the library's per-call scratch through torch's caching allocator
+    (blocks are tied to the call's stream, so later work on it may reuse them
+    in stream order), or back to hipMallocAsync.  Process-wide: switch only
+    while no call is in flight."""
+    global _allocator
+    if on:
+        a = Allocator(ALLOC_FN(_torch_alloc), FREE_FN(_torch_free), None)
+        _check(lib().hf_set_allocator(C.byref(a)))
+        _allocator = a
+    else:
+        _check(lib().hf_set_allocator(None))
+        _allocator = None
 
 
 def timing_enable(on: bool = True):

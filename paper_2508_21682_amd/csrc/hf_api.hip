@@ -163,6 +163,9 @@ hf_status check_forest(const hf_forest* f) {
 }
 
 }  // namespace
+
+ScratchAlloc g_scratch = {{nullptr, nullptr, nullptr}, false};
+ScratchAlloc scratch_allocator() { return g_scratch; }
 }  // namespace hf
 
 using namespace hf;
@@ -183,6 +186,18 @@ const char* hf_status_str(hf_status s) {
 }
 
 const char* hf_last_error(void) { return g_err.c_str(); }
+
+hf_status hf_set_allocator(const hf_allocator* a) {
+  hf::clear_error();
+  if (!a) {
+    hf::g_scratch.on = false;
+    return HF_OK;
+  }
+  HF_ARG(a->alloc && a->free, "an allocator needs both alloc and free");
+  hf::g_scratch.a = *a;
+  hf::g_scratch.on = true;
+  return HF_OK;
+}
 
 hf_status hf_timing_enable(int32_t on) {
   t_on = on != 0;

@@ -48,19 +48,43 @@ struct Err {
   } while (0)
 
 // ---------------------------------------------------------------- workspace
-// Device buffers owned by one call; freed (stream-ordered) on scope exit.
+// The caller's scratch allocator (hf_set_allocator); `on` false: hipMallocAsync.
+struct ScratchAlloc {
+  hf_allocator a;
+  bool on;
+};
+ScratchAlloc scratch_allocator();
+
+// Device buffers owned by one call; freed (stream-ordered) on scope exit,
+// through the allocator that was registered when the call started.
 struct Workspace {
   hipStream_t stream;
+  ScratchAlloc al;
   std::vector<void*> ptrs;
-  explicit Workspace(hipStream_t s) : stream(s) {}
+  explicit Workspace(hipStream_t s) : stream(s), al(scratch_allocator()) {}
   ~Workspace() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, stream);
+    for (void* p : ptrs) {
+      if (al.on)
+        al.a.free(p, al.a.ctx, (void*)stream);
+      else
+        (void)hipFreeAsync(p, stream);
+    }
   }
   template <class T>
   hf_status alloc(T** out, size_t count) {
     void* p = nullptr;
     size_t bytes = count * sizeof(T);
     if (bytes == 0) bytes = 16;
+    if (al.on) {
+      p = al.a.alloc(bytes, al.a.ctx, (void*)stream);
+      if (!p) {
+        set_error("the caller's allocator returned no memory for %zu bytes", bytes);
+        return HF_ERR_OOM;
+      }
+      ptrs.push_back(p);
+      *out = static_cast<T*>(p);
+      return HF_OK;
+    }
     hipError_t e = hipMallocAsync(&p, bytes, stream);
     if (e != hipSuccess) {
       set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));

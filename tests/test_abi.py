@@ -66,10 +66,27 @@ def test_invalid_arguments_rejected_on_host(hf):
     assert b"struct_size" in L.hf_last_error()
     p = hf.ForestParams(C.sizeof(hf.ForestParams), 0, 100, hf.HF_QUANT_AUTO, 1, 2, 0, 0, None)
     assert L.hf_build_forest(dummy, 0, 100, 8, C.byref(p), None, C.byref(out)) == 1
+    p = hf.ForestParams(C.sizeof(hf.ForestParams), 4097, 100, hf.HF_QUANT_AUTO, 1, 2, 0, 0, None)
+    assert L.hf_build_forest(dummy, 0, 100, 8, C.byref(p), None, C.byref(out)) == 1
+    assert b"n_trees" in L.hf_last_error()
     g = hf.GraphParams(C.sizeof(hf.GraphParams), 4, 60, 15, 0, hf.HF_QUANT_AUTO, 0, 1, 2, None)
     assert L.hf_knn_graph(dummy, 0, 100, 8, C.byref(g), dummy, dummy, None) == 1  # 2w >= N
     g = hf.GraphParams(C.sizeof(hf.GraphParams), 4, 8, 15, 3, hf.HF_QUANT_AUTO, 0, 1, 2, None)
     assert L.hf_knn_graph(dummy, 0, 100, 8, C.byref(g), dummy, dummy, None) == 1  # k2 < k
+
+
+def test_allocator_registration_on_host(hf):
+    """hf_set_allocator: NULL restores the default, an allocator needs both
+    callbacks (no device work is involved in either)."""
+    L = hf.lib()
+    assert L.hf_set_allocator(None) == 0
+    assert L.hf_set_allocator(C.byref(hf.Allocator())) == 1
+    assert b"alloc and free" in L.hf_last_error()
+    a = hf.Allocator(hf.ALLOC_FN(lambda n, c, s: None), hf.FREE_FN(lambda p, c, s: None), None)
+    assert L.hf_set_allocator(C.byref(a)) == 0
+    assert L.hf_set_allocator(None) == 0
+    hf.use_torch_allocator(False)
+    hf.restore_default_allocator()
 
 
 def test_graph_arguments_rejected_on_host(hf):

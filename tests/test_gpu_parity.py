@@ -213,6 +213,62 @@ def test_forest_search_many_trees(hf, orc):
     _forest_case(hf, orc, x, q, T=1100, M=20, seed=3, sk_seed=4, params=[(6, 40, 1, 5), (37, 200, 0, 10)])
 
 
+def test_caller_allocator(hf):
+    """Per-call scratch through the caller's allocator (hf_set_allocator):
+    a counting wrapper of torch's caching allocator (the binding's default)
+    and hipMallocAsync (the library's own default) give bit-identical
+    results, every block taken is given back, and an allocator that returns
+    no memory fails the call with HF_ERR_OOM before any device work (no
+    kernel runs on unallocated scratch)."""
+    import ctypes
+    import torch
+
+    x, q = datagen.mixture(20000, 64, 16, 0.1, 81, dtype=np.float16, query_seed=82, nq=200)
+    xd, qd = dev(x), dev(q)
+    fo = hf.Forest(xd, n_trees=6, leaf_max=50, seed=3, sketch_seed=4)
+    ids0, sc0 = fo.search(qd, 10, 200, 100, 1)
+    g0, gs0 = hf.knn_graph(xd, 4, 16, 10, 5)
+    torch.cuda.synchronize()
+    counts = {"alloc": 0, "free": 0}
+
+    def al(n, c, s):
+        counts["alloc"] += 1
+        return hf._torch_alloc(n, c, s)
+
+    def fr(p, c, s):
+        counts["free"] += 1
+        hf._torch_free(p, c, s)
+
+    a = hf.Allocator(hf.ALLOC_FN(al), hf.FREE_FN(fr), None)
+    assert hf.lib().hf_set_allocator(ctypes.byref(a)) == 0
+    try:
+        ids1, sc1 = fo.search(qd, 10, 200, 100, 1)
+        g1, gs1 = hf.knn_graph(xd, 4, 16, 10, 5)
+        torch.cuda.synchronize()
+    finally:
+        hf.restore_default_allocator()
+    assert counts["alloc"] > 0 and counts["alloc"] == counts["free"], counts
+    assert (ids1.cpu().numpy() == ids0.cpu().numpy()).all() and (sc1.cpu().numpy() == sc0.cpu().numpy()).all()
+    assert (g1.cpu().numpy() == g0.cpu().numpy()).all() and (gs1.cpu().numpy() == gs0.cpu().numpy()).all()
+
+    bad = hf.Allocator(hf.ALLOC_FN(lambda n, c, s: None), hf.FREE_FN(lambda p, c, s: None), None)
+    assert hf.lib().hf_set_allocator(ctypes.byref(bad)) == 0
+    try:
+        with pytest.raises(hf.HFError) as err:
+            fo.search(qd, 10, 200, 100, 1)
+        assert err.value.status == 3
+    finally:
+        hf.restore_default_allocator()
+    hf.use_torch_allocator(False)  # hipMallocAsync
+    try:
+        ids2, sc2 = fo.search(qd, 10, 200, 100, 1)
+        torch.cuda.synchronize()
+    finally:
+        hf.restore_default_allocator()
+    assert (ids2.cpu().numpy() == ids0.cpu().numpy()).all()
+    fo.free()
+
+
 def test_forest_duplicates_overflow_selection(hf, orc):
     """All points identical: one oversized leaf, every candidate at Hamming 0,
     more candidates than the selection buffer holds (position-split path)."""

@@ -170,6 +170,62 @@ __device__ __forceinline__ void scan_entries(const uint16_t* __restrict__ hq,
   }
 }
 
+// Keys of every entry whose distance lies in [hf, hb], when no position bound
+// applies (all of them are wanted), in two phases: the row is scanned with
+// four 16-byte loads in flight per thread and the wanted entry indices are
+// appended to keys[] (one LDS atomic per wavefront and step); then each
+// thread takes wanted entries and loads their positions and distances, all
+// of these loads in flight together (a position load under the scan's branch
+// would be waited for entry by entry).  The caller's histogram bounds the
+// count by CAP.
+__device__ __forceinline__ void collect_bins(const uint16_t* __restrict__ hq,
+                                             const uint32_t* __restrict__ tree_perm, int64_t N,
+                                             const uint32_t* __restrict__ wq, int len, int64_t total,
+                                             int hf, int hb, int pos_bits, uint32_t* keys,
+                                             uint32_t* s_cnt) {
+  const int64_t n8 = (total + 7) / 8;
+  const int lane = threadIdx.x & 63;
+  for (int64_t j0 = 0; j0 < n8; j0 += 4 * SEL_T) {
+    uint4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = j0 + u * SEL_T + threadIdx.x;
+      v[u] = *(const uint4*)(hq + 8 * (j < n8 ? j : n8 - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = j0 + u * SEL_T + threadIdx.x;
+      const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int hv = (int)((w[s >> 1] >> (16 * (s & 1))) & 0xFFFFu);
+        const int64_t e = 8 * j + s;
+        const bool want = e < total && hv >= hf && hv <= hb;
+        const uint64_t m = __ballot(want);
+        if (m) {
+          const int leader = __ffsll((unsigned long long)m) - 1;
+          uint32_t base = 0;
+          if (lane == leader) base = atomicAdd(s_cnt, (uint32_t)__popcll(m));
+          base = (uint32_t)__shfl((int)base, leader);
+          const uint32_t slot = base + (uint32_t)__popcll(m & lanemask_lt());
+          if (want && slot < (uint32_t)CAP) keys[slot] = (uint32_t)e;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int cnt = (int)min(*s_cnt, (uint32_t)CAP);
+  __syncthreads();
+  if (threadIdx.x == 0) *s_cnt = (uint32_t)cnt;
+  for (int i = threadIdx.x; i < cnt; i += SEL_T) {
+    const uint32_t e = keys[i];
+    const uint32_t t = e / (uint32_t)len, off = e - t * (uint32_t)len;
+    const uint32_t p = tree_perm[(int64_t)t * N + wq[t] + off];
+    const int hv = (int)hq[e];
+    keys[i] = ((uint32_t)(hv - hf) << pos_bits) | p;
+  }
+}
+
 __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ tree_perm,
                                                   int64_t N, int T, int len, int64_t qstride,
                                                   const uint32_t* __restrict__ win,
@@ -284,7 +340,9 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
       const uint32_t plo = s_plo, pend = s_pend;
       const int lh = lo_ham;
       const uint32_t lp = lo_pos;
-      if (mode == 1) {
+      if (mode == 1 && lp == 0) {
+        collect_bins(hq, tree_perm, N, wq, len, total, hf, hb, pos_bits, keys, &s_cnt);
+      } else if (mode == 1) {
         scan_entries(hq, tree_perm, N, wq, len, total, [&](int hv) { return hv >= hf && hv <= hb; },
                      [&](int hv, uint32_t p) {
                        if (hv > lh || p >= lp) keys[atomicAdd(&s_cnt, 1u)] = ((uint32_t)(hv - hf) << pos_bits) | p;

@@ -49,6 +49,45 @@ __global__ __launch_bounds__(256) void k_descend(const uint32_t* __restrict__ no
   win[q * T + t] = (uint32_t)s;
 }
 
+// The same walk with the codes of the block's 64 queries staged in LDS: a
+// wavefront per tree, a lane per query, so each level waits for one global
+// load (the node) instead of two (the node, then the code byte it tests).
+// Rows of d bytes, d a multiple of 16 and at most DS_MAXD.
+constexpr int DS_Q = 64, DS_MAXD = 512;
+__global__ __launch_bounds__(256) void k_descend_lds(const uint32_t* __restrict__ nodes,
+                                                     const int64_t* __restrict__ node_off,
+                                                     const uint8_t* __restrict__ qcodes, int64_t nq,
+                                                     int d, int T, int64_t N, int k1, int max_steps,
+                                                     uint32_t* __restrict__ win) {
+  extern __shared__ __align__(16) uint8_t sc[];  // DS_Q x d code bytes (dynamic LDS)
+  const int64_t q0 = (int64_t)blockIdx.x * DS_Q;
+  const int nqb = (int)min<int64_t>(DS_Q, nq - q0);
+  const int c16 = d / 16;
+  for (int i = threadIdx.x; i < nqb * c16; i += 256)
+    ((uint4*)sc)[i] = ((const uint4*)(qcodes + q0 * d))[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (lane >= nqb || t >= T) return;
+  const uint32_t* nd = nodes + 2 * node_off[t];
+  const uint8_t* u = sc + lane * d;
+  uint32_t idx = 0;
+  int64_t mid = 0;
+  for (int step = 0; step < max_steps; ++step) {
+    uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
+    if (r.y >> 31) {
+      mid = (int64_t)r.x + (int64_t)((r.y & 0x7FFFFFFFu) >> 1);
+      break;
+    }
+    uint32_t a = r.y & 0xFFFFu, L = (r.y >> 16) & 7u, flip = (r.y >> 19) & 1u;
+    uint32_t bit = ((u[a] >> L) & 1u) ^ flip;
+    idx = bit ? r.x : idx + 1u;
+  }
+  int64_t s = mid - k1 / 2, smax = N - k1 > 0 ? N - k1 : 0;
+  s = s < 0 ? 0 : (s > smax ? smax : s);
+  win[(q0 + lane) * T + t] = (uint32_t)s;
+}
+
 // ---------------------------------------------------------------- ham + hist
 constexpr int HB = 513;  // Hamming values 0..512
 
@@ -565,9 +604,15 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   if (!win) HF_TRY(ws.alloc(&win, (size_t)(nq * T)));
   const int64_t* doff = f->node_off_dev;
   {
-    dim3 grid((unsigned)ceil_div(nq, 256), (unsigned)T);
     StageTimer tm(ST_DESCEND, s);
-    k_descend<<<grid, 256, 0, s>>>(f->nodes, doff, qcodes, nq, d, T, N, (int)p.k1, 8 * d + 2, win);
+    if (d % 16 == 0 && d <= DS_MAXD) {
+      dim3 grid((unsigned)ceil_div(nq, DS_Q), (unsigned)ceil_div(T, 4));
+      k_descend_lds<<<grid, 256, (size_t)DS_Q * d, s>>>(f->nodes, doff, qcodes, nq, d, T, N, (int)p.k1,
+                                                         8 * d + 2, win);
+    } else {
+      dim3 grid((unsigned)ceil_div(nq, 256), (unsigned)T);
+      k_descend<<<grid, 256, 0, s>>>(f->nodes, doff, qcodes, nq, d, T, N, (int)p.k1, 8 * d + 2, win);
+    }
     HF_LAUNCH_CHECK();
   }
   // the second stage runs in batches of queries sized to bound scratch memory

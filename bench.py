@@ -4,7 +4,7 @@
 Default workload ("search-23Mx384"): 23,000,000 x 384 fp16 points of a seeded
 8,192-component Gaussian mixture on the sphere, 10,000 queries from the same
 mixture, a forest of 1,024 trees with leaves of at most 100 points, 512-bit SRP
-sketches, k1 = 95, k2 = 950, h = 1, k = 30 by inner product with an FP32
+sketches, k1 = 90, k2 = 950, h = 1, k = 30 by inner product with an FP32
 rerank (the shape of the paper's Task 1; the budget is the cheapest found at
 recall@30 >= 0.7 on this data).  One step = one hf_search call over the whole query batch
 (descent of every tree, Hamming filter, expansion, rerank); the forest is
@@ -423,7 +423,7 @@ def main():
     ap.add_argument("--trees", type=int, default=1024)
     ap.add_argument("--leaf", type=int, default=100)
     ap.add_argument("--k", type=int, default=None)
-    ap.add_argument("--k1", type=int, default=95)
+    ap.add_argument("--k1", type=int, default=90)
     ap.add_argument("--k2", type=int, default=950)
     ap.add_argument("--h", type=int, default=1)
     ap.add_argument("--orders", type=int, default=232)

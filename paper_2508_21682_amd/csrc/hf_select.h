@@ -7,41 +7,37 @@
 
 namespace hf {
 
-__device__ __forceinline__ void bitonic_u32(uint32_t* a, int n2) {
+// Bitonic sort of a[0..n2) in LDS by the whole workgroup (n2 a power of two,
+// blockDim.x a multiple of 64).  A stage compares n2/2 pairs, pair p on
+// thread p mod blockDim.x: elements i = ((p & ~(j-1)) << 1) | (p & (j-1))
+// and i + j.  While j <= 32 the pairs of one wavefront's p-range stay in a
+// 128-element run that this wavefront alone touches in every such stage, so
+// those stages are separated by wavefront syncs; a workgroup barrier follows
+// every stage with j >= 64, every stage before one, and the last stage.
+template <class T>
+__device__ __forceinline__ void bitonic_lds(T* a, int n2) {
+  const int half = n2 >> 1;
   for (int k = 2; k <= n2; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        int ixj = i ^ j;
-        if (ixj > i) {
-          uint32_t x = a[i], y = a[ixj];
-          bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
+      for (int p = threadIdx.x; p < half; p += blockDim.x) {
+        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+        const T x = a[i], y = a[i + j];
+        if ((x > y) == ((i & k) == 0)) {
+          a[i] = y;
+          a[i + j] = x;
         }
       }
-      __syncthreads();
+      const int jn = j > 1 ? j >> 1 : k;  // j of the next stage (k doubles after j = 1)
+      if (j > 32 || jn > 32 || (j == 1 && k == n2))
+        __syncthreads();
+      else
+        wave_lds_sync();
     }
 }
 
-__device__ __forceinline__ void bitonic_u64(uint64_t* a, int n2) {
-  for (int k = 2; k <= n2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-        int ixj = i ^ j;
-        if (ixj > i) {
-          uint64_t x = a[i], y = a[ixj];
-          bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-}
+__device__ __forceinline__ void bitonic_u32(uint32_t* a, int n2) { bitonic_lds(a, n2); }
+
+__device__ __forceinline__ void bitonic_u64(uint64_t* a, int n2) { bitonic_lds(a, n2); }
 
 __device__ __forceinline__ float ordered_to_float(uint32_t o) {
   uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;

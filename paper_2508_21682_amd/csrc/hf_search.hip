@@ -434,7 +434,7 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
 }
 
 // ------------------------------------------------------------------ rerank
-constexpr int RR_T = 512;
+constexpr int RR_T = 256;  // six workgroups a CU: their sort, row and select phases overlap
 
 constexpr int RROWS = 4;
 

@@ -61,7 +61,7 @@ typedef enum hf_sketch_kind { HF_SKETCH_SRP = 0, HF_SKETCH_LEARNED = 1 } hf_sket
 typedef struct hf_forest hf_forest;
 typedef struct hf_lhash hf_lhash;
 
-/* Build parameters (Section 3.1 "Key Hyperparameters": n trees; leaves of
+/* Build parameters (Section 3.1, key hyperparameters: n trees; leaves of
  * about M points).  struct_size must be sizeof(hf_forest_params). */
 typedef struct hf_forest_params {
   uint32_t struct_size;
@@ -110,8 +110,8 @@ const char* hf_last_error(void);
 
 /* ---------------------------------------------------------- building blocks */
 
-/* Curves of trees 0..T-1 (Algorithm 1 "randomized axis orders"; Algorithm 2
- * "randomly permute coordinate axes"), computed on the host from one
+/* Curves of trees 0..T-1 (Algorithms 1 and 2: a random axis order per tree or
+ * order), computed on the host from one
  * SplitMix64 stream seeded with `seed`: per tree a Fisher-Yates shuffle of the
  * axes, then ceil(d/64) words whose bits (LSB first) mark reflected axes.
  * perm_host[t*d + i] = data axis read by tree axis i; refl_host[t*d + i] = 1
@@ -126,7 +126,7 @@ hf_status hf_quant_exp(const void* X_dev, hf_dtype dtype, int64_t n_elems, int32
                        void* stream);
 
 /* 8-bit ordering codes u = clamp(floor(x * 2^e) + 128, 0, 255), element-wise
- * (the data's "vector quantization" step of Algorithms 1 and 2, here only
+ * (the quantization step of Algorithms 1 and 2, here only
  * used to order points). codes_dev: n_elems bytes. */
 hf_status hf_quantize(const void* X_dev, hf_dtype dtype, int64_t n_elems, int32_t e,
                       uint8_t* codes_dev, void* stream);
@@ -189,8 +189,8 @@ hf_status hf_forest_pos2id(const hf_forest* f, uint32_t* pos2id_dev, void* strea
 hf_status hf_forest_sketches(const hf_forest* f, uint64_t* sk_dev, void* stream);
 
 /* Algorithm 1 for a batch of nq queries (same dtype as the data):
- *  first stage: every query descends every tree (the collective "simulated
- *    Hilbert sort"); its window is the k1 tree positions centred on the
+ *  first stage: every query descends every tree (the whole batch located
+ *    along every curve at once, Section 3.1); its window is the k1 tree positions centred on the
  *    midpoint of the leaf reached, shifted inside [0, N);
  *  second stage: C2 = the k2 candidates of the union of the windows with the
  *    smallest (Hamming distance of sketches, master position);

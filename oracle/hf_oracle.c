@@ -40,8 +40,8 @@ uint64_t hfo_splitmix64(uint64_t seed, int64_t index) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Curves, one per tree (Alg. 1 "randomized axis orders"; Alg. 2 "randomly   */
-/* permute coordinate axes").  One SplitMix64 stream seeded with `seed` is   */
+/* Curves, one per tree (Alg. 1 and Alg. 2: a random axis order per tree or */
+/* order).  One SplitMix64 stream seeded with `seed` is                      */
 /* consumed tree after tree: first a Fisher-Yates shuffle of the identity    */
 /* (for i = d-1 down to 1: j = next mod (i+1), swap), then ceil(d/64) words  */
 /* whose bits (LSB first) say which tree axes are reflected (x -> 255 - x).  */
@@ -88,7 +88,7 @@ static double val(const void *x, int32_t dtype, int64_t i) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* 8-bit ordering codes (Alg. 1 / Alg. 2 "vector quantization"; the paper    */
+/* 8-bit ordering codes (the quantization step of Alg. 1 / Alg. 2; the paper */
 /* gives no codec for the ordering, so one power-of-two scale is used):      */
 /*   e = largest integer in [-8, 24] with 2^e*max < 128 and 2^e*min >= -128  */
 /*       over the data (-8 if none);  u = clamp(floor(x*2^e) + 128, 0, 255). */
@@ -334,8 +334,8 @@ int64_t hfo_trie(const uint64_t *keys, const uint32_t *order, int64_t N, int32_t
 }
 
 /* ------------------------------------------------------------------------ */
-/* Collective descent (Section 3.1 "simulate the Hilbert sort for all        */
-/* queries"; Alg. 1 first stage).  From the root, bit = ((u_q[a] >> L) & 1)  */
+/* Collective descent (Section 3.1: all queries located along each tree's    */
+/* curve at once; Alg. 1 first stage).  From the root, bit = ((u_q[a] >> L) & 1)  */
 /* ^ flip; 0 goes left (next node), 1 goes right.  At the leaf [lo,hi) the   */
 /* query's position is read as the leaf midpoint and the k1 candidates as    */
 /* the centred window: s = clamp(floor((lo+hi)/2) - floor(k1/2), 0,          */

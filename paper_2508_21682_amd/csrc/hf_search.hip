@@ -1,6 +1,6 @@
 // Search path of Algorithm 1 on the GPU:
-//   descend   - every (query, tree) pair walks its tree: the collective
-//               "simulated Hilbert sort" of the whole batch (first stage);
+//   descend   - every (query, tree) pair walks its tree: the whole batch
+//               located along every curve at once (first stage);
 //   ham       - streams each query's n*k1 window entries (duplicates
 //               included, as the paper counts them), gathers 64-byte
 //               sketches 16 bytes per lane and writes Hamming distances plus

@@ -207,10 +207,13 @@ def test_forest_search_large_candidate_sets(hf, orc):
 
 
 def test_forest_search_many_trees(hf, orc):
-    """1,100 trees: more window starts per query than 1,024 (the Hamming
-    filter keeps them in LDS sized by the tree count)."""
+    """1,100 and 4,096 trees (the limit): more window starts per query than
+    1,024 (the Hamming filter keeps them in LDS sized by the tree count)."""
     x, q = datagen.mixture(2000, 8, 6, 0.1, 71, unit=False, dtype=np.float32, query_seed=72, nq=24)
     _forest_case(hf, orc, x, q, T=1100, M=20, seed=3, sk_seed=4, params=[(6, 40, 1, 5), (37, 200, 0, 10)])
+    # the largest forest the library accepts (4,096 trees)
+    x, q = datagen.mixture(2000, 8, 6, 0.1, 73, unit=False, dtype=np.float32, query_seed=74, nq=16)
+    _forest_case(hf, orc, x, q, T=4096, M=20, seed=5, sk_seed=6, params=[(5, 30, 1, 5)])
 
 
 def test_caller_allocator(hf):

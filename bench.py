@@ -3,8 +3,8 @@
 
 Default workload ("search-23Mx384"): 23,000,000 x 384 fp16 points of a seeded
 8,192-component Gaussian mixture on the sphere, 10,000 queries from the same
-mixture, a forest of 1,024 trees with leaves of at most 100 points, 512-bit SRP
-sketches, k1 = 90, k2 = 950, h = 1, k = 30 by inner product with an FP32
+mixture, a forest of 1,280 trees with leaves of at most 100 points, 512-bit SRP
+sketches, k1 = 70, k2 = 1100, h = 0, k = 30 by inner product with an FP32
 rerank (the shape of the paper's Task 1; the budget is the cheapest found at
 recall@30 >= 0.7 on this data).  One step = one hf_search call over the whole query batch
 (descent of every tree, Hamming filter, expansion, rerank); the forest is
@@ -239,6 +239,19 @@ def bench_search(args, hf, torch, ws):
     hf.timing_enable(False)
     rec = recall(ids, gt)
     qps = nq * args.steps / dt
+    alt = None
+    if args.alt:
+        a1, a2, ah = (int(v) for v in args.alt.split(","))
+        forest.search(q, args.k, a1, a2, ah)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            aids, _ = forest.search(q, args.k, a1, a2, ah)
+        torch.cuda.synchronize()
+        adt = time.perf_counter() - t
+        alt = {"k1": a1, "k2": a2, "h": ah, "recall": recall(aids, gt), "qps": nq * args.steps / adt,
+               "ms_per_step": adt * 1e3 / args.steps}
+        log("alternative budget k1=%d k2=%d h=%d: recall %.4f, %.0f QPS" % (a1, a2, ah, alt["recall"], alt["qps"]))
     log("recall@%d %.4f, %.0f QPS, stages %s" % (args.k, rec, qps,
                                                   {k: round(v[0] / args.steps, 2) for k, v in stages.items()}))
     # roofline of the dominant kernel: the Hamming filter streams n*k1 window
@@ -263,7 +276,7 @@ def bench_search(args, hf, torch, ws):
            "config": {"workload": args.workload, "n": N, "d": d, "queries": nq, "trees": T,
                       "leaf_max": args.leaf, "k": args.k, "k1": args.k1, "k2": args.k2, "h": args.h,
                       "sketch_bits": 512, "rerank": "fp32"},
-           "build_s": build_s, "roofline": roof, "brute_force": brute,
+           "build_s": build_s, "roofline": roof, "brute_force": brute, "alt_budget": alt,
            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
     if sweep:
         res["sweep"] = sweep
@@ -420,12 +433,15 @@ def main():
     ap.add_argument("--workload", default="search-23Mx384", choices=["search-23Mx384", "graph-3Mx384"])
     ap.add_argument("--n", type=int, default=None, help="override N (development runs only)")
     ap.add_argument("--nq", type=int, default=None)
-    ap.add_argument("--trees", type=int, default=1024)
+    ap.add_argument("--trees", type=int, default=1280)
     ap.add_argument("--leaf", type=int, default=100)
     ap.add_argument("--k", type=int, default=None)
-    ap.add_argument("--k1", type=int, default=90)
-    ap.add_argument("--k2", type=int, default=950)
-    ap.add_argument("--h", type=int, default=1)
+    ap.add_argument("--k1", type=int, default=70)
+    ap.add_argument("--k2", type=int, default=1100)
+    ap.add_argument("--h", type=int, default=0)
+    ap.add_argument("--alt", default="65,1000,1",
+                    help="search: a second budget 'k1,k2,h' timed on the same forest ('' for none); the default "
+                         "is the fastest found at recall >= 0.7 that keeps the +-h expansion")
     ap.add_argument("--orders", type=int, default=232)
     ap.add_argument("--window", type=int, default=160)
     ap.add_argument("--sweep", default=None,

@@ -1,6 +1,6 @@
 """Checks at the benchmark's full sizes, in the configuration bench.py times.
 
-The oracle cannot rebuild 1,024 trees over 23M points inside a test, so the
+The oracle cannot rebuild 1,280 trees over 23M points inside a test, so the
 23M x 384 search is checked on sampled outputs the oracle computes one by one
 and on properties that hold at any size:
 
@@ -65,7 +65,7 @@ def test_search_23M_sampled(hf, orc):
 
     w = datagen.WORKLOADS["search-23Mx384"]
     N, d = w["n"], w["d"]
-    T, M, k, k1, k2, h = 1024, 100, 30, 90, 950, 1
+    T, M, k, k1, k2, h = 1280, 100, 30, 70, 1100, 0
     print("drawing %d x %d" % (N, d), flush=True)
     x = datagen.mixture_device(N, d, w["n_comp"], w["sigma"], w["seed"], w["unit"])
     q = datagen.mixture_device(2000, d, w["n_comp"], w["sigma"], w["seed"], w["unit"],
@@ -84,7 +84,7 @@ def test_search_23M_sampled(hf, orc):
 
     print("key order and self descent", flush=True)
     perm, refl = orc.curves(5, T, d)
-    for t in [0, 1, 512, 1023]:
+    for t in [0, 1, 640, 1279]:
         tp = _u32(fo.perm(t))
         i = rng.choice(N - 1, 300, replace=False)
         a, b = pos2id[tp[i]], pos2id[tp[i + 1]]
@@ -119,7 +119,7 @@ def test_search_23M_sampled(hf, orc):
         tp = fo.perm(t)
         s = torch.from_numpy(win[:, t].astype(np.int64))[:, None] + torch.arange(k1)[None, :]
         got = tp[s.cuda()].cpu().numpy().view(np.uint32)
-        if t % 128 == 0:
+        if t % 160 == 0:
             nodes = _u32(fo.nodes(t)).reshape(-1, 2)
             for j in range(len(qs)):
                 lo, size = _descend(nodes, qcodes[j])

@@ -315,15 +315,20 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
           hf = h;
           break;
         }
-      // bins from hf on until they hold twice `need` entries (plus 64), or
-      // CAP: the entries of smallest distance are the query's near
-      // neighbours, which sit in the windows of many trees, so duplicates
-      // are common there; a round short of `need` distinct entries would
-      // cost two more scans of the query's row (histogram, collection)
+      // bins from hf on until they hold `enough` entries, or CAP.  The
+      // entries of smallest distance are the query's near neighbours, which
+      // sit in the windows of many trees, so duplicates are common there and
+      // a round short of `need` distinct entries would cost two more scans
+      // of the query's row: at least 1.5 need + 64, and up to 64 below the
+      // power of two that the bitonic sort pads that to (the sort costs the
+      // same for any count up to it)
       int hb = -1;
       if (hf >= 0) {
         uint32_t cum = 0;
-        const uint32_t enough = 2u * (uint32_t)need + 64u;
+        const uint32_t lo = (uint32_t)need + (uint32_t)need / 2u + 64u;
+        uint32_t p2 = 1;
+        while (p2 < lo) p2 <<= 1;
+        const uint32_t enough = max(lo, p2 - 64u);
         for (int h = hf; h < HB && h - hf < HM; ++h) {
           if (cum + hist[h] > (uint32_t)CAP) break;
           cum += hist[h];

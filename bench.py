@@ -442,7 +442,7 @@ def main():
     ap.add_argument("--alt", default="65,1000,1",
                     help="search: a second budget 'k1,k2,h' timed on the same forest ('' for none); the default "
                          "is the fastest found at recall >= 0.7 that keeps the +-h expansion")
-    ap.add_argument("--orders", type=int, default=232)
+    ap.add_argument("--orders", type=int, default=228)
     ap.add_argument("--window", type=int, default=160)
     ap.add_argument("--sweep", default=None,
                     help="extra configs: search 'k1,k2,h;...', graph 'orders,w[,k2];...'")

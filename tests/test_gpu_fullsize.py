@@ -16,7 +16,7 @@ and on properties that hold at any size:
 
 The 1M x 384 plain graph (6 orders, window +-32) is small enough for the
 oracle to sort in full: its sampled rows are compared exactly.  The 3M x 384
-graph in the benchmark's configuration (232 orders, +-160, k=15) is checked
+graph in the benchmark's configuration (228 orders, +-160, k=15) is checked
 on sampled rows: cosines equal FP64 recomputations, sorted, distinct
 neighbours other than the row itself.
 """
@@ -175,7 +175,7 @@ def test_graph_3M_bench_config_sampled(hf):
     w = datagen.WORKLOADS["graph-3Mx384"]
     print("drawing 3M x 384", flush=True)
     x = datagen.mixture_device(w["n"], w["d"], w["n_comp"], w["sigma"], w["seed"], w["unit"])
-    gi, gs = hf.knn_graph(x, 232, 160, 15, 3)
+    gi, gs = hf.knn_graph(x, 228, 160, 15, 3)
     rows = np.random.default_rng(2).choice(w["n"], 2000, replace=False)
     gi, gs = gi.cpu().numpy()[rows], gs.cpu().numpy()[rows]
     X = _rows(x, rows).astype(np.float64)

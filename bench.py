@@ -125,6 +125,18 @@ def recall(found, truth):
     return hit / float(truth.numel())
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), for the CPU-baseline record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline_search(args):
     """The oracle (untuned, all host threads) on a bounded sample of the search workload."""
     import numpy as np
@@ -142,7 +154,7 @@ def cpu_baseline_search(args):
     oracle.search(F, q, args.k1, args.k2, args.h, args.k)
     dt = time.perf_counter() - t
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nq_s / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
+    return {"value": nq_s / dt, "unit": "queries/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "oracle search (Alg. 1 stages after the build) of %d queries on a %d x %d "
                       "sample of the same mixture recipe (%d components), %d trees instead of %d, "
                       "k1=%d k2=%d h=%d k=%d; %.2f s" % (nq_s, n_s, w["d"], comps, t_s, args.trees,
@@ -171,7 +183,7 @@ def cpu_baseline_graph(args):
     # candidate lists with orders x rows
     f_o = args.orders / o_s
     est = t_sort * f_o * (w["n"] / n_s) + t_rows * f_o * (w["n"] / rows_s)
-    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
+    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "oracle graph on a %d x %d sample of the same recipe: %d orders sorted in %.2f s, "
                       "candidate lists (w=%d, k=%d) of %d rows in %.2f s; value = sort time x (%d/%d orders) "
                       "x (%d/%d points) + row time x (%d/%d orders) x (%d/%d rows)"

@@ -671,11 +671,15 @@ void hfo_mlp_forward(const void *x, int32_t dtype, int64_t n, int32_t d, int32_t
         if (fabs(z1[j]) <= delta) {
           move[j] = fabs(a[j]) + delta; /* relu kink: a may be 0 or a small value */
         } else if (z1[j] > 0.0 && rounded) {
+          /* a in [2^(e-1), 2^e): bf16 values there are 2^(e-8) apart.  The
+           * value below a is 2^(e-8) away too, except when a = 2^(e-1) is a
+           * power of two, where the binade below has half that spacing. */
           int e;
           frexp(a[j], &e);
-          double u = ldexp(1.0, e - 9); /* the smaller of the two spacings around a */
-          double lo_mid = a[j] - u / 2, hi_mid = a[j] + ldexp(1.0, e - 8) / 2;
-          if (fabs(z1[j] - lo_mid) <= delta || fabs(z1[j] - hi_mid) <= delta) move[j] = ldexp(1.0, e - 8);
+          double up = ldexp(1.0, e - 8);
+          double down = a[j] == ldexp(1.0, e - 1) ? ldexp(1.0, e - 9) : up;
+          double lo_mid = a[j] - down / 2, hi_mid = a[j] + up / 2;
+          if (fabs(z1[j] - lo_mid) <= delta || fabs(z1[j] - hi_mid) <= delta) move[j] = up;
         }
       }
       for (int32_t j = 0; j < 512; ++j) {

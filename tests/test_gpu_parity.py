@@ -56,6 +56,9 @@ def first_diff_bits(keys, order):
 def check_topk(gi, gs, oi, os_, x, q, k):
     """Rank-wise scores within TOL; differing ids only at near-ties of the k-th score."""
     assert gi.shape == oi.shape
+    for row in gi:  # a result lists each id once
+        v = row[row >= 0]
+        assert np.unique(v).size == v.size, row
     fin = np.isfinite(os_)
     assert (np.isfinite(gs) == fin).all()
     assert np.abs(gs[fin] - os_[fin]).max() <= TOL
@@ -495,10 +498,21 @@ def test_lhash_gradients_match_oracle(hf, orc):
     loss, g = L.grad(dev(A), dev(B), tp)
     oloss, og = orc.lhash_grad(A, B, *W, slope=2.0, tau=0.2, lam=0.05, rounded=True)
     assert abs(loss - oloss) <= 1e-4 * max(1.0, abs(oloss))
-    for gg, oo in zip(g, og):
-        gg = gg.cpu().numpy().astype(np.float64)
-        rel = np.linalg.norm(gg - oo) / max(np.linalg.norm(oo), 1e-12)
-        assert rel <= 2e-3, rel
+    # element by element: |g - g_oracle| <= RTOL |g_oracle| + ATOL * max|g_oracle| of the tensor.
+    # The GPU sums the 2B rows and the inner products in FP32 (relative error a
+    # few 2^-24 times the sum of magnitudes, which cancellation can make large
+    # against a small entry), and a hidden activation whose pre-activation lies
+    # at a bf16 rounding midpoint may round the other way (one bf16 step,
+    # 2^-8 relative, in one of the 2B rows).  Both stay far below ATOL of the
+    # tensor's scale; a wrong row or column (a transposed operand, a dropped
+    # term) moves entries by their own size.
+    RTOL, ATOL = 2e-3, 2e-4
+    for name, gg, oo in zip(["W1", "b1", "W2", "b2"], g, og):
+        gg = gg.cpu().numpy().astype(np.float64).reshape(oo.shape)
+        lim = RTOL * np.abs(oo) + ATOL * np.abs(oo).max()
+        worst = np.max(np.abs(gg - oo) / lim)
+        print("gradient %s: worst |diff| / bound = %.3g" % (name, worst))
+        assert (np.abs(gg - oo) <= lim).all(), (name, worst)
     L.free()
 
 

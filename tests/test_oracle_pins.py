@@ -136,7 +136,7 @@ def test_hilbert_order1_2d_u_shape(orc):
     assert order == [(0, 0), (0, 1), (1, 1), (1, 0)]
 
 
-@pytest.mark.parametrize("d", [1, 2, 5, 10])
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 10])
 def test_hilbert_B1_is_gray_code(orc, d):
     """B=1: the curve visits the cube corners in binary-reflected Gray-code order, axis 0 MSB."""
     for h in range(1 << d):
@@ -489,3 +489,204 @@ def test_lhash_gradients_match_finite_differences(orc):
             num = (vals[0] - vals[1]) / (np.float64(np.float32(old + h)) - np.float64(np.float32(old - h)))
             ana = g[pi].reshape(-1)[idx]
             assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)) + 1e-7, (pi, idx, num, ana)
+
+
+# ----------------------------------------------------------------- pins added for the precision and learned forms
+def _bf16_bits(x):
+    """bf16 rounding of binary64 values by integer arithmetic on their bits:
+    keep the sign, the exponent and the top 7 fraction bits, rounding the 45
+    dropped bits to nearest with ties to an even kept part."""
+    u = np.asarray(x, np.float64).view(np.uint64)
+    lo = u & np.uint64((1 << 45) - 1)
+    hi = u >> np.uint64(45)
+    up = (lo > np.uint64(1 << 44)) | ((lo == np.uint64(1 << 44)) & ((hi & np.uint64(1)) == 1))
+    hi = hi + up.astype(np.uint64)
+    return (hi << np.uint64(45)).view(np.float64)
+
+
+def test_bf16_bit_helper_against_float32_path():
+    """The test's own binary64 helper agrees with the float32 bit recipe on values
+    that are exact in binary32 (no double rounding there)."""
+    import struct
+
+    rng = np.random.default_rng(21)
+    xs = rng.standard_normal(500).astype(np.float32).astype(np.float64)
+    for x in xs:
+        u = struct.unpack("<I", struct.pack("<f", x))[0]
+        hi, lo = u >> 16, u & 0xFFFF
+        if lo > 0x8000 or (lo == 0x8000 and (hi & 1)):
+            hi += 1
+        assert _bf16_bits(x) == struct.unpack("<f", struct.pack("<I", hi << 16))[0]
+
+
+def test_lhash_rounded_forward_against_bit_arithmetic(orc):
+    """The deployed (bf16-rounded) forward equals a numpy MLP whose roundings are
+    done on the bits of binary64 values."""
+    W1, b1, W2, b2 = _small_net(11, d=40, hid=24)
+    x = np.random.default_rng(12).standard_normal((9, 40)).astype(np.float32)
+    z1, a, z2, band = orc.mlp_forward(x, W1, b1, W2, b2, rounded=True)
+    X = _bf16_bits(x.astype(np.float64))
+    ref1 = X @ _bf16_bits(W1.astype(np.float64)).T + b1.astype(np.float64)
+    refa = _bf16_bits(np.maximum(ref1, 0.0))
+    ref2 = refa @ _bf16_bits(W2.astype(np.float64)).T + b2.astype(np.float64)
+    assert np.allclose(z1, ref1, rtol=0, atol=1e-12)
+    assert (a == refa).all()
+    assert np.allclose(z2, ref2, rtol=0, atol=1e-12)
+    assert (band >= 0).all()
+
+
+@pytest.mark.parametrize("a_val,below", [(1.5, True), (1.5, False), (1.0, True), (1.0, False),
+                                          (0.75, True), (3.25, False)])
+def test_lhash_band_flags_rounding_midpoints(orc, a_val, below):
+    """A hidden pre-activation next to either rounding midpoint of its bf16 value
+    (the lower one of a non-power-of-two value lies a half spacing 2^(e-9) below
+    it, the lower one of a power of two 2^(e-10)) must put every output bit that
+    depends on it in the fragile band, with a margin of at least one bf16 step of
+    the activation times the weight."""
+    e = int(np.frexp(a_val)[1])  # a_val in [2^(e-1), 2^e)
+    up = 2.0 ** (e - 8)
+    down = 2.0 ** (e - 9) if a_val == 2.0 ** (e - 1) else up
+    mid = a_val - down / 2 if below else a_val + up / 2
+    # z1 = W1 * bf16(x) + b1 with W1 = 1, x = 1 (exact in bf16); b1 carries the value
+    eps = 2.0 ** -20
+    z1_target = mid + (eps if below else -eps)  # on a_val's side of the midpoint
+    b1 = np.array([z1_target - 1.0], np.float32)
+    assert float(b1[0]) + 1.0 == z1_target
+    W1 = np.ones((1, 1), np.float32)
+    W2 = np.full((512, 1), 0.5, np.float32)
+    b2 = np.zeros(512, np.float32)
+    z1, a, z2, band = orc.mlp_forward(np.ones((1, 1), np.float32), W1, b1, W2, b2, rounded=True)
+    assert z1[0, 0] == z1_target and a[0, 0] == a_val
+    assert (band[0] >= 0.5 * min(up, down)).all(), (band[0, 0], up, down)
+    # the other side of the midpoint really does round to the neighbour value
+    other = _bf16_bits(np.array([mid - (eps if below else -eps)]))[0]
+    assert other != a_val and abs(other - a_val) <= max(up, down)
+
+
+def test_lhash_band_quiet_away_from_midpoints(orc):
+    """Far from every midpoint and from the relu kink the band is only the
+    summation term (2^-16 of the magnitudes)."""
+    W1 = np.ones((1, 1), np.float32)
+    b1 = np.array([0.25 + 2.0 ** -12], np.float32)  # z1 = 1.25 + 2^-12, far inside the cell of 1.25
+    W2 = np.full((512, 1), 0.5, np.float32)
+    b2 = np.zeros(512, np.float32)
+    _, a, z2, band = orc.mlp_forward(np.ones((1, 1), np.float32), W1, b1, W2, b2, rounded=True)
+    assert a[0, 0] == 1.25
+    assert np.allclose(band[0], 2.0 ** -16 * np.abs(z2[0]), rtol=1e-12)
+
+
+# e4m3 values from the format's definition (bias 7, 3 fraction bits, subnormals
+# below 2^-6, no infinities, 0x7F/0xFF NaN), independent of the oracle's codec
+E4M3_POS = np.array([(m / 8.0) * 2.0 ** -6 if E == 0 else (1 + m / 8.0) * 2.0 ** (E - 7)
+                     for E in range(16) for m in range(8)][:0x7F])
+
+
+def test_fp8_scale_rule(orc):
+    rng = np.random.default_rng(31)
+    x = (rng.standard_normal((40, 24)) * rng.uniform(1e-3, 10, (40, 1))).astype(np.float32)
+    x[5] = 0.0
+    for r in range(x.shape[0]):
+        s = orc.lib().hfo_fp8_scale(x.ctypes.data, 1, r, x.shape[1])
+        m = float(np.abs(x[r]).max())
+        if m == 0.0:
+            assert s == 1.0
+            continue
+        # s is max|x| / 448 to binary32 precision ...
+        assert abs(s * 448.0 - m) <= 2.0 ** -23 * m
+        # ... so the largest element encodes to the largest finite code and none saturates beyond it
+        codes = [orc.e4m3_encode(float(np.float32(v) / np.float32(s))) for v in x[r]]
+        assert orc.e4m3_encode(float(np.float32(m) / np.float32(s))) == 0x7E
+        assert all((c & 0x7F) <= 0x7E for c in codes)
+
+
+def _lowprec_case(orc, x, q, c2_sets, h, k, prec, S):
+    N, d = x.shape
+    F = dict(x=x, N=N, d=d, pos2id=np.arange(N, dtype=np.uint32))
+    k2 = max(len(c) for c in c2_sets)
+    c2 = np.full((len(c2_sets), k2), 0xFFFFFFFF, np.uint32)
+    c2n = np.array([len(c) for c in c2_sets], np.int32)
+    for i, c in enumerate(c2_sets):
+        c2[i, :len(c)] = c
+    return orc.search_lowprec(F, q, c2, c2n, h, k, prec, S), c2, c2n
+
+
+def _expansion(c2_set, h, N):
+    return sorted({p for r in c2_set for p in range(max(0, r - h), min(N - 1, r + h) + 1)})
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_lowprec_exact_when_values_are_representable(orc, prec):
+    """Rows and queries made of values the format holds exactly (for FP8: e4m3
+    values times a power of two, with an element at 448 times it, so the
+    scale is that power of two): the low-precision scores are then the exact
+    inner products, the survivors are the first S of E by (exact score desc,
+    position asc), built here with Python sets and sorting, and the result is
+    the FP64 top-k of the survivors.  Duplicate rows make ties at the cut."""
+    rng = np.random.default_rng(41 if prec == "bf16" else 42)
+    N, d, nq, h, k, S = 90, 16, 6, 1, 5, 12
+    if prec == "bf16":
+        vals = _bf16_bits(rng.standard_normal((N + nq, d)))
+    else:
+        pick = rng.integers(0, 0x7F, (N + nq, d))
+        vals = E4M3_POS[pick] * rng.choice([-1.0, 1.0], (N + nq, d))
+        vals[:, 0] = 448.0 * rng.choice([-1.0, 1.0], N + nq)
+        vals *= (2.0 ** -rng.integers(3, 12, (N + nq, 1)))
+    vals = vals.astype(np.float32)
+    x, q = vals[:N].copy(), vals[N:].copy()
+    x[31] = x[30]  # tied rows
+    x[61] = x[60]
+    c2_sets = [sorted(rng.choice(N, size=rng.integers(3, 15), replace=False).tolist()) for _ in range(nq)]
+    c2_sets[0] = [30, 31, 60, 61, 0, 89]
+    res, _, _ = _lowprec_case(orc, x, q, c2_sets, h, k, prec, S)
+    X, Q = x.astype(np.float64), q.astype(np.float64)
+    for i in range(nq):
+        E = _expansion(c2_sets[i], h, N)
+        exact = {p: float(Q[i] @ X[p]) for p in E}
+        surv = sorted(E, key=lambda p: (-exact[p], p))[:S]
+        ns = len(surv)
+        assert res["surv_pos"][i][:ns].tolist() == surv
+        assert (res["surv_pos"][i][ns:] == 0xFFFFFFFF).all()
+        assert res["surv_score"][i][:ns].tolist() == [exact[p] for p in surv]
+        top = sorted(surv, key=lambda p: (-exact[p], p))[:k]
+        assert res["ids"][i][:len(top)].tolist() == top
+        assert (res["ids"][i][len(top):] == -1).all()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_lowprec_scores_within_format_error(orc, prec):
+    """On general values every survivor's low-precision score lies within the
+    rounding error of the format of the exact inner product (bf16: relative
+    2^-9 per operand; e4m3: relative 2^-4 per normal operand, absolute half the
+    smallest subnormal 2^-10 times the scale below 2^-6), the survivors are
+    positions of E (Python sets) in non-increasing score order, and the
+    result is the FP64 top-k over them."""
+    rng = np.random.default_rng(43)
+    N, d, nq, h, k, S = 200, 24, 8, 2, 6, 15
+    x = rng.standard_normal((N, d)).astype(np.float32)
+    q = rng.standard_normal((nq, d)).astype(np.float32)
+    c2_sets = [sorted(rng.choice(N, size=10, replace=False).tolist()) for _ in range(nq)]
+    res, _, _ = _lowprec_case(orc, x, q, c2_sets, h, k, prec, S)
+    X, Q = x.astype(np.float64), q.astype(np.float64)
+
+    def op_err(v):
+        if prec == "bf16":
+            return 2.0 ** -9 * np.abs(v)
+        s = np.abs(v).max() / 448.0
+        return np.maximum(2.0 ** -4 * np.abs(v), 2.0 ** -10 * s) * (1 + 2.0 ** -20)
+
+    for i in range(nq):
+        E = set(_expansion(c2_sets[i], h, N))
+        sp = res["surv_pos"][i]
+        ns = min(S, len(E))
+        got = sp[:ns].tolist()
+        assert len(set(got)) == ns and set(got) <= E
+        sc = res["surv_score"][i][:ns]
+        assert (np.diff(sc) <= 0).all()
+        eq = op_err(Q[i])
+        for p, s in zip(got, sc):
+            ex = op_err(X[p])
+            bound = np.sum(np.abs(Q[i]) * ex + np.abs(X[p]) * eq + eq * ex) + 1e-12
+            assert abs(s - Q[i] @ X[p]) <= bound
+        exact = {p: float(Q[i] @ X[p]) for p in got}
+        top = sorted(got, key=lambda p: (-exact[p], p))[:k]
+        assert res["ids"][i].tolist() == top

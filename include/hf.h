@@ -211,6 +211,23 @@ hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype,
                           uint32_t* win_dev, uint32_t* c2_dev, int32_t* c2n_dev, int32_t* en_dev,
                           void* stream);
 
+/* hf_search without any device allocation, for callers that cannot allocate
+ * device memory (work under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, checks and results as hf_search.
+ * Every scratch buffer is carved from one fixed array of
+ * HF_NOALLOC_SCRATCH_MIB MiB that the library holds on each GPU it runs on
+ * until the process ends; queries are processed in consecutive chunks sized
+ * to fit it, in stream order.  A configuration whose single query needs more
+ * than the array (about 2 * n_trees * k1 + 4 * (n_trees + k2) + d bytes)
+ * returns HF_ERR_UNSUPPORTED without launching anything.  All calls on one
+ * GPU share that GPU's array: calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race on it and must be
+ * serialised by the caller.  The array keeps the last call's contents; no
+ * result depends on them. */
+#define HF_NOALLOC_SCRATCH_MIB 64
+hf_status hf_search_noalloc(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64_t nq,
+                            const hf_search_params* params, int32_t* ids_dev, float* scores_dev, void* stream);
+
 /* Precision form (not in the paper): adds a BF16 copy (RNE of the stored
  * rows) or an FP8 copy (OCP e4m3, per-row scale s = max|x|/448 in FP32, codes
  * of x/s rounded to nearest even and saturated) of the master-ordered rows to

@@ -31,7 +31,7 @@ EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_qu
            "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name", "hf_forest_add_precision",
            "hf_search_lowprec_debug", "hf_audit_scores", "hf_lhash_create", "hf_lhash_free", "hf_lhash_get",
            "hf_lhash_encode", "hf_lhash_grad", "hf_lhash_train", "hf_forest_set_sketch",
-           "hf_knn_graph_debug", "hf_set_allocator"]
+           "hf_knn_graph_debug", "hf_set_allocator", "hf_search_noalloc"]
 N_STAGES = 16
 
 
@@ -121,6 +121,7 @@ def lib():
             "hf_forest_sketches": (C.c_int, [P, P, P]),
             "hf_search": (C.c_int, [P, P, C.c_int, i64, P, P, P, P]),
             "hf_search_debug": (C.c_int, [P, P, C.c_int, i64, P, P, P, P, P, P, P, P]),
+            "hf_search_noalloc": (C.c_int, [P, P, C.c_int, i64, P, P, P, P]),
             "hf_knn_graph": (C.c_int, [P, C.c_int, i64, i32, P, P, P, P]),
             "hf_timing_enable": (C.c_int, [i32]),
             "hf_timing_read": (C.c_int, [P, P]),
@@ -352,6 +353,20 @@ class Forest:
         p = self._params(k, k1, k2, h, precision, survivors)
         _check(lib().hf_search(self._h, _ptr(q), _dtype(q), q.shape[0], C.byref(p), _ptr(ids), _ptr(sc),
                                _stream()))
+        return ids, sc
+
+    def search_noalloc(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32", survivors: int = 0,
+                       out=None):
+        """hf_search_noalloc: the library allocates nothing (scratch from its fixed
+        per-device array); ``out`` = (ids, scores) lets the caller bring the outputs too."""
+        q = _dev(q)
+        t = _torch()
+        if out is None:
+            out = (_empty((q.shape[0], k), t.int32, q), _empty((q.shape[0], k), t.float32, q))
+        ids, sc = out
+        p = self._params(k, k1, k2, h, precision, survivors)
+        _check(lib().hf_search_noalloc(self._h, _ptr(q), _dtype(q), q.shape[0], C.byref(p), _ptr(ids), _ptr(sc),
+                                       _stream()))
         return ids, sc
 
     def set_sketch(self, kind: str, lhash=None):

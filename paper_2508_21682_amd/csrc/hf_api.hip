@@ -81,10 +81,6 @@ void make_curves(uint64_t seed, int T, int d, int32_t* perm, uint8_t* refl) {
   }
 }
 
-hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_search_params& p,
-                        int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
-                        int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
-                        hipStream_t s);
 hf_status graph_launch(const void* X, hf_dtype dt, int64_t N, int d, const hf_graph_params& p,
                        int e, int32_t* ids, float* scores, int32_t* c2_ids, hipStream_t s);
 
@@ -624,3 +620,10 @@ hf_status hf_knn_graph_debug(const void* X_dev, hf_dtype dtype, int64_t N, int32
 }
 
 }  // extern "C"
+
+namespace hf {
+hf_status search_args_ok(const hf_forest* f, const void* Q, hf_dtype dtype, int64_t nq, const hf_search_params* p,
+                         const void* ids, const void* scores) {
+  return check_search(f, Q, dtype, nq, p, ids, scores);
+}
+}  // namespace hf

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -56,12 +57,18 @@ struct ScratchAlloc {
 ScratchAlloc scratch_allocator();
 
 // Device buffers owned by one call; freed (stream-ordered) on scope exit,
-// through the allocator that was registered when the call started.
+// through the allocator that was registered when the call started.  In arena
+// mode (the second constructor) buffers are carved, 256-byte aligned, from a
+// caller-provided device region and nothing is allocated or freed.
 struct Workspace {
   hipStream_t stream;
   ScratchAlloc al;
   std::vector<void*> ptrs;
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
   explicit Workspace(hipStream_t s) : stream(s), al(scratch_allocator()) {}
+  Workspace(hipStream_t s, void* region, size_t bytes)
+      : stream(s), al{{nullptr, nullptr, nullptr}, false}, arena((char*)region), arena_cap(bytes) {}
   ~Workspace() {
     for (void* p : ptrs) {
       if (al.on)
@@ -70,11 +77,24 @@ struct Workspace {
         (void)hipFreeAsync(p, stream);
     }
   }
+  // bytes an arena needs for buffers of these sizes (each rounded up to 256)
+  static size_t arena_bytes(size_t bytes) { return (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255; }
   template <class T>
   hf_status alloc(T** out, size_t count) {
     void* p = nullptr;
     size_t bytes = count * sizeof(T);
     if (bytes == 0) bytes = 16;
+    if (arena) {
+      const size_t need = arena_bytes(bytes);
+      if (arena_used + need > arena_cap) {
+        set_error("scratch region of %zu bytes exhausted (%zu more needed)", arena_cap,
+                  arena_used + need - arena_cap);
+        return HF_ERR_UNSUPPORTED;
+      }
+      *out = reinterpret_cast<T*>(arena + arena_used);
+      arena_used += need;
+      return HF_OK;
+    }
     if (al.on) {
       p = al.a.alloc(bytes, al.a.ctx, (void*)stream);
       if (!p) {
@@ -269,8 +289,22 @@ hf_status gpf_order(const uint64_t* sk, const uint32_t* order, int64_t N, int w,
 hf_status gpf_final(const void* X, const float* nrm, int64_t N, int d, const uint64_t* lists, int k2, int k,
                     int32_t* ids, float* sc, int32_t* c2_ids, hipStream_t s);
 // hf_lhash.hip
-hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_t N, uint64_t* sk, hipStream_t s);
+// ws (nullable): where the hidden-layer staging comes from (a call's own
+// workspace otherwise)
+hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_t N, uint64_t* sk, hipStream_t s,
+                           Workspace* ws = nullptr);
+// hf_search.hip: Algorithm 1 for nq queries; scratch from ws when given
+hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_search_params& p,
+                        int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
+                        int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
+                        hipStream_t s, Workspace* ws = nullptr);
+// hf_api.hip: the argument checks of hf_search
+hf_status search_args_ok(const hf_forest* f, const void* Q, hf_dtype dtype, int64_t nq, const hf_search_params* p,
+                         const void* ids, const void* scores);
+// scratch bytes search_launch takes from an arena for nq queries
+size_t search_scratch_bytes(const hf_forest* f, int64_t nq, const hf_search_params& p);
 int lhash_dim(const hf_lhash* L);
+int lhash_hidden(const hf_lhash* L);
 // host helpers (hf_api.hip)
 void make_curves(uint64_t seed, int T, int d, int32_t* perm, uint8_t* refl);
 uint64_t splitmix64_next(uint64_t* state);

@@ -427,9 +427,11 @@ hf_status check_lhash(const hf_lhash* L) {
 
 }  // namespace
 
-hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_t N, uint64_t* sk, hipStream_t s) {
+hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_t N, uint64_t* sk, hipStream_t s,
+                           Workspace* ext) {
   HF_TRY(check_lhash(L));
-  Workspace ws(s);
+  Workspace own(s);
+  Workspace& ws = ext ? *ext : own;
   const int64_t chunk = std::min<int64_t>(N, 1 << 20);
   uint16_t* H;
   HF_TRY(ws.alloc(&H, (size_t)chunk * L->hid));
@@ -442,6 +444,7 @@ hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_
 }
 
 int lhash_dim(const hf_lhash* L) { return (L && L->magic == HF_LHASH_MAGIC) ? L->d : 0; }
+int lhash_hidden(const hf_lhash* L) { return (L && L->magic == HF_LHASH_MAGIC) ? L->hid : 0; }
 
 }  // namespace hf
 

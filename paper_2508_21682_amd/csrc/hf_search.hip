@@ -580,11 +580,35 @@ __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64
 }  // namespace
 
 // ------------------------------------------------------------------ host side
+// Entries of one query's row of distances: T windows of len, padded to 256.
+int64_t ham_row_entries(int T, int len) { return ((int64_t)T * len + 255) / 256 * 256; }
+
+// Queries per filter batch: rows of distances of a batch stay under 2 GB.
+int64_t filter_batch(int64_t nq, int64_t per_q) {
+  int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1ll << 31) / (per_q * 2 + 1)));
+  return ceil_div(nq, ceil_div(nq, batch));  // equal batches
+}
+
+size_t search_scratch_bytes(const hf_forest* f, int64_t nq, const hf_search_params& p) {
+  const int T = f->T;
+  const int len = (int)std::min<int64_t>(p.k1, f->N);
+  const int64_t per_q = ham_row_entries(T, len);
+  const int64_t batch = filter_batch(nq, per_q);
+  auto A = [](size_t b) { return Workspace::arena_bytes(b); };
+  size_t total = A((size_t)nq * f->d) + A((size_t)nq * 64) + A((size_t)nq * T * 4) +
+                 A((size_t)batch * per_q * 2) + A((size_t)batch * HB * 4) + A((size_t)nq * p.k2 * 4) +
+                 A((size_t)nq * 4);
+  if (f->sketch_kind == HF_SKETCH_LEARNED)
+    total += A((size_t)std::min<int64_t>(nq, 1 << 20) * lhash_hidden(f->lhash) * 2);  // bf16 hidden layer
+  return total;
+}
+
 hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_search_params& p,
                         int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
                         int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
-                        hipStream_t s) {
-  Workspace ws(s);
+                        hipStream_t s, Workspace* ext) {
+  Workspace own(s);
+  Workspace& ws = ext ? *ext : own;
   const int64_t N = f->N;
   const int d = f->d, T = f->T;
   const int len = (int)std::min<int64_t>(p.k1, N);
@@ -601,7 +625,7 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   {
     StageTimer tm(ST_QSKETCH, s);
     if (f->sketch_kind == HF_SKETCH_LEARNED)
-      HF_TRY(lhash_encode_dev(f->lhash, Q, f->dtype, nq, qsk, s));
+      HF_TRY(lhash_encode_dev(f->lhash, Q, f->dtype, nq, qsk, s, &ws));
     else
       HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws, f->srp_R));
   }
@@ -621,9 +645,8 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     HF_LAUNCH_CHECK();
   }
   // the second stage runs in batches of queries sized to bound scratch memory
-  const int64_t per_q = ((int64_t)T * len + 255) / 256 * 256;  // rows of distances padded to 256 entries
-  int64_t batch = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1ll << 31) / (per_q * 2 + 1)));
-  batch = ceil_div(nq, ceil_div(nq, batch));  // equal batches
+  const int64_t per_q = ham_row_entries(T, len);
+  const int64_t batch = filter_batch(nq, per_q);
   uint16_t* ham;
   uint32_t *hist, *c2 = c2_out;
   int32_t* c2n = c2n_out;

@@ -66,47 +66,77 @@ def log(*a):
 T0 = time.time()
 
 
-def ground_truth_ip(x, q, k, xchunk=1 << 20, qchunk=2500):
-    """Exact top-k by inner product (FP32 on the GPU), for recall only."""
+def _rescore_topk(rows_fp64, cand, k):
+    """Top-k of candidate ids by (FP64 score desc, id asc); rows_fp64(cand) gives the scores."""
     import torch
 
-    nq = q.shape[0]
-    best_s = torch.full((nq, k), -float("inf"), device=x.device)
-    best_i = torch.zeros((nq, k), dtype=torch.int64, device=x.device)
+    sc = rows_fp64(cand)
+    # sort by id first, then stably by score: ties keep the smaller id first
+    o = torch.argsort(cand, dim=1)
+    cand, sc = torch.gather(cand, 1, o), torch.gather(sc, 1, o)
+    o = torch.argsort(-sc, dim=1, stable=True)
+    return torch.gather(cand, 1, o)[:, :k]
+
+
+def ground_truth_ip(x, q, k, xchunk=1 << 20, qchunk=2500, extra=64):
+    """Exact top-k by inner product: an FP32 screen on the GPU keeps the best
+    k + 64 of all N rows, which are rescored in FP64 and re-sorted (score desc,
+    id asc).  For recall only."""
+    import torch
+
+    nq, kk = q.shape[0], k + extra
+    best_s = torch.full((nq, kk), -float("inf"), device=x.device)
+    best_i = torch.zeros((nq, kk), dtype=torch.int64, device=x.device)
     qf = q.float()
     for xs in range(0, x.shape[0], xchunk):
         xf = x[xs:xs + xchunk].float()
         for qs in range(0, nq, qchunk):
             S = qf[qs:qs + qchunk] @ xf.T
-            s, i = torch.topk(S, k, dim=1)
+            s, i = torch.topk(S, min(kk, S.shape[1]), dim=1)
             cs = torch.cat([best_s[qs:qs + qchunk], s], 1)
             ci = torch.cat([best_i[qs:qs + qchunk], i + xs], 1)
-            s2, j = torch.topk(cs, k, dim=1)
+            s2, j = torch.topk(cs, kk, dim=1)
             best_s[qs:qs + qchunk] = s2
             best_i[qs:qs + qchunk] = torch.gather(ci, 1, j)
             del S
         del xf
-    return best_i
+    out = torch.empty((nq, k), dtype=torch.int64, device=x.device)
+    qd = q.double()
+    for qs in range(0, nq, qchunk):
+        qq = qd[qs:qs + qchunk]
+        out[qs:qs + qchunk] = _rescore_topk(
+            lambda c: (x[c].double() * qq[:, None, :]).sum(-1), best_i[qs:qs + qchunk], k)
+    return out
 
 
-def ground_truth_graph(x, rows, k, xchunk=1 << 20):
+def ground_truth_graph(x, rows, k, xchunk=1 << 20, extra=64):
+    """Exact k-NN graph rows by cosine, self excluded: FP32 screen of the best
+    k + 64, FP64 rescore and re-sort (cosine desc, id asc)."""
     import torch
 
     xn = x.float()
     xn = xn / torch.linalg.vector_norm(xn, dim=1, keepdim=True)
     q = xn[rows]
-    best_s = torch.full((rows.numel(), k), -float("inf"), device=x.device)
-    best_i = torch.zeros((rows.numel(), k), dtype=torch.int64, device=x.device)
+    kk = k + extra
+    best_s = torch.full((rows.numel(), kk), -float("inf"), device=x.device)
+    best_i = torch.zeros((rows.numel(), kk), dtype=torch.int64, device=x.device)
     for xs in range(0, x.shape[0], xchunk):
         S = q @ xn[xs:xs + xchunk].T
         self_hit = (rows >= xs) & (rows < xs + S.shape[1])
         S[self_hit.nonzero().flatten(), (rows[self_hit] - xs)] = -float("inf")
-        s, i = torch.topk(S, k, dim=1)
+        s, i = torch.topk(S, min(kk, S.shape[1]), dim=1)
         cs = torch.cat([best_s, s], 1)
         ci = torch.cat([best_i, i + xs], 1)
-        s2, j = torch.topk(cs, k, dim=1)
+        s2, j = torch.topk(cs, kk, dim=1)
         best_s, best_i = s2, torch.gather(ci, 1, j)
-    return best_i
+    xd = x.double()
+    nd = torch.linalg.vector_norm(xd, dim=1)
+    out = torch.empty((rows.numel(), k), dtype=torch.int64, device=x.device)
+    for s0 in range(0, rows.numel(), 2500):
+        r = rows[s0:s0 + 2500]
+        out[s0:s0 + 2500] = _rescore_topk(
+            lambda c: (xd[c] * xd[r][:, None, :]).sum(-1) / (nd[r, None] * nd[c]), best_i[s0:s0 + 2500], k)
+    return out
 
 
 def audit(hf, torch, x, q, ids, scores):
@@ -137,58 +167,114 @@ def cpu_model():
     return None
 
 
-def cpu_baseline_search(args):
-    """The oracle (untuned, all host threads) on a bounded sample of the search workload."""
+def _set_affinity_all_threads(cpus):
+    """CPU affinity of every thread of this process (OpenMP's pool included)."""
+    for tid in os.listdir("/proc/self/task"):
+        try:
+            os.sched_setaffinity(int(tid), cpus)
+        except OSError:
+            pass
+
+
+def cpu_runs(fn):
+    """fn(threads) timed twice in this process: on every core the process may
+    use (OpenMP at its default thread count), then on 8 of them with 8 OpenMP
+    threads (the paper's 8-core limit).  Returns [(record, cores), ...]."""
+    import oracle
+
+    allowed = sorted(os.sched_getaffinity(0))
+    threads_all = oracle.set_num_threads(1)
+    oracle.set_num_threads(threads_all)
+    out = [(fn(threads_all), {"threads": threads_all, "cpus": len(allowed), "pinned": False})]
+    eight = set(allowed[:8])
+    try:
+        _set_affinity_all_threads(eight)
+        oracle.set_num_threads(len(eight))
+        out.append((fn(len(eight)), {"threads": len(eight), "cpus": len(eight), "pinned": True}))
+    finally:
+        oracle.set_num_threads(threads_all)
+        _set_affinity_all_threads(set(allowed))
+    return out
+
+
+def cpu_baseline_search(args, gpu_entries_per_s):
+    """The oracle (untuned) on a bounded sample of the search workload, with as
+    many window entries per query as the GPU run (16 trees x n k1 / 16 each):
+    the Hamming filter's work per query is matched, the data set is smaller."""
     import numpy as np
 
     import datagen
     import oracle
 
-    n_s, t_s, nq_s = 100_000, 16, 5_000
-    w = datagen.WORKLOADS[args.workload]
+    n_s, t_s, nq_s = 100_000, 16, 1_000
+    k1_s = min(n_s, args.trees * args.k1 // t_s)
+    w = datagen.WORKLOADS["search-23Mx384"]
     comps = max(1, round(w["n_comp"] * n_s / w["n"]))
     x, q = datagen.mixture(n_s, w["d"], comps, w["sigma"], w["seed"], dtype=np.float16,
                            query_seed=w["query_seed"], nq=nq_s)
     F = oracle.build_forest(x, T=t_s, M=args.leaf, seed=5, sketch_seed=6)
-    t = time.perf_counter()
-    oracle.search(F, q, args.k1, args.k2, args.h, args.k)
-    dt = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nq_s / dt, "unit": "queries/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
-            "sample": "oracle search (Alg. 1 stages after the build) of %d queries on a %d x %d "
-                      "sample of the same mixture recipe (%d components), %d trees instead of %d, "
-                      "k1=%d k2=%d h=%d k=%d; %.2f s" % (nq_s, n_s, w["d"], comps, t_s, args.trees,
-                                                         args.k1, args.k2, args.h, args.k, dt)}
+
+    def run(threads):
+        t = time.perf_counter()
+        oracle.search(F, q, k1_s, args.k2, args.h, args.k)
+        return time.perf_counter() - t
+
+    recs = []
+    for dt, c in cpu_runs(run):
+        ent = nq_s * t_s * k1_s / dt
+        recs.append({"value": nq_s / dt, "unit": "queries/s", "cores": c["threads"], "pinned_8": c["pinned"],
+                     "kind": "oracle", "cpu_model": cpu_model(), "window_entries_per_s": ent,
+                     "gpu_over_cpu_per_entry": gpu_entries_per_s / ent,
+                     "sample": "oracle search (Alg. 1 stages after the build) of %d queries on a %d x %d sample "
+                               "of the same mixture recipe (%d components), %d trees x k1=%d window entries per "
+                               "query (the GPU run: %d x %d), k2=%d h=%d k=%d; %.2f s on %d threads%s"
+                               % (nq_s, n_s, w["d"], comps, t_s, k1_s, args.trees, args.k1, args.k2, args.h,
+                                  args.k, dt, c["threads"], " pinned to 8 cores" if c["pinned"] else "")})
+        log("cpu baseline search: %.2f s on %d threads (%.3g window entries/s)" % (dt, c["threads"], ent))
+    res = dict(recs[0])
+    res["pinned_8_cores"] = recs[1] if len(recs) > 1 else None
+    return res
 
 
-def cpu_baseline_graph(args):
+def cpu_baseline_graph(args, n_full):
+    """The oracle graph on a 100K sample (16 orders, 1,000 rows), scaled to the
+    full workload's orders, points and rows."""
     import numpy as np
 
     import datagen
     import oracle
 
     n_s, rows_s, o_s = 100_000, 1_000, min(16, args.orders)
-    w = datagen.WORKLOADS[args.workload]
+    w = datagen.WORKLOADS["graph-3Mx384"]
     comps = max(1, round(w["n_comp"] * n_s / w["n"]))
     x = datagen.mixture(n_s, w["d"], comps, w["sigma"], w["seed"], dtype=np.float16)
-    t = time.perf_counter()
-    orders, _ = oracle.graph_orders(x, o_s, 3)
-    t_sort = time.perf_counter() - t
-    log("cpu baseline: %d oracle orders of %d points in %.2f s" % (o_s, n_s, t_sort))
-    t = time.perf_counter()
-    oracle.graph_rows(x, orders, args.window, args.k, np.arange(rows_s))
-    t_rows = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # sorts scale with orders x points (n log n taken as linear: favours the CPU),
-    # candidate lists with orders x rows
-    f_o = args.orders / o_s
-    est = t_sort * f_o * (w["n"] / n_s) + t_rows * f_o * (w["n"] / rows_s)
-    return {"value": est, "unit": "s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
-            "sample": "oracle graph on a %d x %d sample of the same recipe: %d orders sorted in %.2f s, "
-                      "candidate lists (w=%d, k=%d) of %d rows in %.2f s; value = sort time x (%d/%d orders) "
-                      "x (%d/%d points) + row time x (%d/%d orders) x (%d/%d rows)"
-                      % (n_s, w["d"], o_s, t_sort, args.window, args.k, rows_s, t_rows, args.orders, o_s,
-                         w["n"], n_s, args.orders, o_s, w["n"], rows_s)}
+
+    def run(threads):
+        t = time.perf_counter()
+        orders, _ = oracle.graph_orders(x, o_s, 3)
+        t_sort = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.graph_rows(x, orders, args.window, args.k, np.arange(rows_s))
+        return t_sort, time.perf_counter() - t
+
+    recs = []
+    for (t_sort, t_rows), c in cpu_runs(run):
+        # sorts scale with orders x points (n log n taken as linear: favours the
+        # CPU), candidate lists with orders x rows
+        f_o = args.orders / o_s
+        est = t_sort * f_o * (n_full / n_s) + t_rows * f_o * (n_full / rows_s)
+        recs.append({"value": est, "unit": "s", "cores": c["threads"], "pinned_8": c["pinned"], "kind": "oracle",
+                     "cpu_model": cpu_model(),
+                     "sample": "oracle graph on a %d x %d sample of the same recipe: %d orders sorted in %.2f s, "
+                               "candidate lists (w=%d, k=%d) of %d rows in %.2f s, on %d threads%s; value = sort "
+                               "time x (%d/%d orders) x (%d/%d points) + row time x (%d/%d orders) x (%d/%d rows)"
+                               % (n_s, w["d"], o_s, t_sort, args.window, args.k, rows_s, t_rows, c["threads"],
+                                  " pinned to 8 cores" if c["pinned"] else "", args.orders, o_s, n_full, n_s,
+                                  args.orders, o_s, n_full, rows_s)})
+        log("cpu baseline graph: estimated %.0f s on %d threads" % (est, c["threads"]))
+    res = dict(recs[0])
+    res["pinned_8_cores"] = recs[1] if len(recs) > 1 else None
+    return res
 
 
 def bench_search(args, hf, torch, ws):
@@ -219,22 +305,25 @@ def bench_search(args, hf, torch, ws):
     # exact search scores every (query, point) pair: 2 N d flops per query
     bf_flop = 2.0 * N * d * nq
     brute = {"qps": nq / gt_s, "recall": 1.0,
-             "method": "FP32 GEMM (torch) and torch top-k over 1M-row chunks of all N rows",
+             "method": "FP32 GEMM (torch) and top-(k+64) over 1M-row chunks of all N rows, the k+64 rescored "
+                       "in FP64 and re-sorted",
              "fp16_mfma_ceiling_qps": nq / (bf_flop / (MFMA_F16_PEAK_TFLOPS * 1e12))}
     log("brute force: %.0f QPS (an fp16 MFMA brute force could reach at most %.0f QPS)"
         % (brute["qps"], brute["fp16_mfma_ceiling_qps"]))
     sweep = []
     if args.sweep:
         for cfg in args.sweep.split(";"):
-            k1, k2, h = (int(v) for v in cfg.split(","))
+            v = [int(u) for u in cfg.split(",")]
+            k1, k2, h, tr = v[0], v[1], v[2], (v[3] if len(v) > 3 else 0)
+            forest.search(q, args.k, k1, k2, h, trees=tr)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            ids, _ = forest.search(q, args.k, k1, k2, h)
+            ids, _ = forest.search(q, args.k, k1, k2, h, trees=tr)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             r = recall(ids, gt)
-            sweep.append({"k1": k1, "k2": k2, "h": h, "recall": r, "qps": nq / dt})
-            log("sweep k1=%d k2=%d h=%d: recall %.4f, %.0f QPS" % (k1, k2, h, r, nq / dt))
+            sweep.append({"k1": k1, "k2": k2, "h": h, "trees": tr or args.trees, "recall": r, "qps": nq / dt})
+            log("sweep k1=%d k2=%d h=%d trees=%d: recall %.4f, %.0f QPS" % (k1, k2, h, tr or args.trees, r, nq / dt))
             hf.timing_read()
     for _ in range(args.warmup):
         forest.search(q, args.k, args.k1, args.k2, args.h)
@@ -264,6 +353,21 @@ def bench_search(args, hf, torch, ws):
         alt = {"k1": a1, "k2": a2, "h": ah, "recall": recall(aids, gt), "qps": nq * args.steps / adt,
                "ms_per_step": adt * 1e3 / args.steps}
         log("alternative budget k1=%d k2=%d h=%d: recall %.4f, %.0f QPS" % (a1, a2, ah, alt["recall"], alt["qps"]))
+    c3 = None
+    if args.c3:
+        # the same data, queries and k at 160 trees (the forest's first 160:
+        # tree t does not depend on the trees after it)
+        c1_, c2_, ch_, ct_ = (int(v) for v in args.c3.split(","))
+        forest.search(q, args.k, c1_, c2_, ch_, trees=ct_)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            cids, _ = forest.search(q, args.k, c1_, c2_, ch_, trees=ct_)
+        torch.cuda.synchronize()
+        cdt = time.perf_counter() - t
+        c3 = {"trees": ct_, "k1": c1_, "k2": c2_, "h": ch_, "recall": recall(cids, gt),
+              "qps": nq * args.steps / cdt, "ms_per_step": cdt * 1e3 / args.steps}
+        log("%d trees k1=%d k2=%d h=%d: recall %.4f, %.0f QPS" % (ct_, c1_, c2_, ch_, c3["recall"], c3["qps"]))
     log("recall@%d %.4f, %.0f QPS, stages %s" % (args.k, rec, qps,
                                                   {k: round(v[0] / args.steps, 2) for k, v in stages.items()}))
     # roofline of the dominant kernel: the Hamming filter streams n*k1 window
@@ -288,7 +392,8 @@ def bench_search(args, hf, torch, ws):
            "config": {"workload": args.workload, "n": N, "d": d, "queries": nq, "trees": T,
                       "leaf_max": args.leaf, "k": args.k, "k1": args.k1, "k2": args.k2, "h": args.h,
                       "sketch_bits": 512, "rerank": "fp32"},
-           "build_s": build_s, "roofline": roof, "brute_force": brute, "alt_budget": alt,
+           "build_s": build_s, "roofline": roof, "brute_force": brute, "alt_budget": alt, "config3": c3,
+           "window_entries_per_s": nq * args.steps * T * ln / dt,
            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
     if sweep:
         res["sweep"] = sweep
@@ -375,17 +480,17 @@ def bench_learned(args, hf, torch, ws, forest, x, q, gt, nq):
             "sketch_in_use": "srp" if lrec <= srec else "learned"}
 
 
-def bench_graph(args, hf, torch, ws):
+def bench_graph(args, hf, torch, ws, k):
     import datagen
 
-    N = args.n or ws["n"]
+    N = (args.n if args.workload.startswith("graph") else None) or ws["n"]
     d = ws["d"]
     log("drawing %d x %d data on the device" % (N, d))
     x = datagen.mixture_device(N, d, ws["n_comp"], ws["sigma"], ws["seed"], ws["unit"])
     torch.cuda.synchronize()
-    if args.sweep:
+    if args.sweep and args.workload.startswith("graph"):
         rows = torch.randperm(N, generator=torch.Generator(device="cpu").manual_seed(4))[:10000].to(x.device)
-        gt = ground_truth_graph(x, rows, args.k)
+        gt = ground_truth_graph(x, rows, k)
         for cfg in args.sweep.split(";"):
             v = [int(u) for u in cfg.split(",")]
             no, wi, k2 = v[0], v[1], (v[2] if len(v) > 2 else 0)
@@ -393,7 +498,7 @@ def bench_graph(args, hf, torch, ws):
             hf.timing_enable(True)
             hf.timing_read()
             t = time.perf_counter()
-            ids, _ = hf.knn_graph(x, no, wi, args.k, 3, k2=k2, sketch_seed=6)
+            ids, _ = hf.knn_graph(x, no, wi, k, 3, k2=k2, sketch_seed=6)
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             st = hf.timing_read()
@@ -402,19 +507,19 @@ def bench_graph(args, hf, torch, ws):
                 no, wi, k2, recall(ids[rows], gt), el,
                 {k_: round(v_[0], 1) for k_, v_ in st.items() if v_[1]}))
     for _ in range(args.warmup):
-        hf.knn_graph(x, args.orders, args.window, args.k, 3)
+        hf.knn_graph(x, args.orders, args.window, k, 3)
     torch.cuda.synchronize()
     hf.timing_enable(True)
     hf.timing_read()
     t = time.perf_counter()
     for _ in range(args.steps):
-        ids, sc = hf.knn_graph(x, args.orders, args.window, args.k, 3)
+        ids, sc = hf.knn_graph(x, args.orders, args.window, k, 3)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     stages = hf.timing_read()
     hf.timing_enable(False)
     rows = torch.randperm(N, generator=torch.Generator(device="cpu").manual_seed(4))[:10000].to(x.device)
-    gt = ground_truth_graph(x, rows, args.k)
+    gt = ground_truth_graph(x, rows, k)
     rec = recall(ids[rows], gt)
     log("graph %.3f s, recall %.4f, stages %s" % (dt / args.steps, rec,
                                                    {k: round(v[0] / args.steps, 2) for k, v in stages.items()}))
@@ -422,10 +527,10 @@ def bench_graph(args, hf, torch, ws):
     # per band launch (one order): every position reads its re-laid row once
     # (2d B), its norm and id (8 B), and reads and writes its top-k list
     # (16k B); neighbours' rows come through the caches
-    bytes_launch = N * (d * 2 + 4 + 4 + args.k * 8 * 2)
+    bytes_launch = N * (d * 2 + 4 + 4 + k * 8 * 2)
     achieved = bytes_launch / (band_ms / band_n * 1e-3) / 1e9
     src = os.path.join(ROOT, "paper_2508_21682_amd", "csrc", "hf_graph.hip")
-    cfg = {"n": N, "orders": args.orders, "window": args.window, "k": args.k}
+    cfg = {"n": N, "orders": args.orders, "window": args.window, "k": k}
     rec_t = measured_traffic("k_band_graph-3Mx384_counters.json", src, cfg)
     roof = {"bound": "hbm", "kernel": "k_band", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": rec_t[0] if rec_t else None,
@@ -433,8 +538,53 @@ def bench_graph(args, hf, torch, ws):
     return {"metric": "kNN-graph build s (3Mx384, k=15)", "value": dt / args.steps, "unit": "s",
             "ms_per_step": dt * 1e3 / args.steps, "recall": rec, "higher_is_better": False,
             "config": {"workload": args.workload, "n": N, "d": d, "orders": args.orders,
-                       "window": args.window, "k": args.k}, "roofline": roof,
+                       "window": args.window, "k": k}, "roofline": roof,
             "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
+
+
+def bench_configs(args, hf, torch):
+    """The two small configurations: the 10,000 x 32 search (8 trees, recall@10
+    against the exact inner-product top-10) and the 1M x 384 graph (16 orders,
+    +-32, recall@15 on 10,000 sampled rows)."""
+    import numpy as np
+
+    import datagen
+
+    out = {}
+    w = datagen.WORKLOADS["search-10Kx32"]
+    x, q = datagen.mixture(w["n"], w["d"], w["n_comp"], w["sigma"], w["seed"], unit=w["unit"], dtype=np.float32,
+                           query_seed=w["query_seed"], nq=w["nq"])
+    x, q = torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda()
+    fo = hf.Forest(x, n_trees=8, leaf_max=100, seed=1, sketch_seed=2)
+    gt = ground_truth_ip(x, q, 10)
+    k1, k2, h = 256, 64, 1
+    fo.search(q, 10, k1, k2, h)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        ids, _ = fo.search(q, 10, k1, k2, h)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    fo.free()
+    out["search-10Kx32"] = {"trees": 8, "leaf_max": 100, "k": 10, "k1": k1, "k2": k2, "h": h,
+                            "recall": recall(ids, gt), "qps": q.shape[0] / dt, "ms_per_step": dt * 1e3}
+    log("search-10Kx32: recall@10 %.4f, %.3f ms per 1,000 queries" % (out["search-10Kx32"]["recall"], dt * 1e3))
+    w = datagen.WORKLOADS["graph-1Mx384"]
+    x = datagen.mixture_device(w["n"], w["d"], w["n_comp"], w["sigma"], w["seed"], w["unit"])
+    hf.knn_graph(x, 16, 32, 15, 3)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        gids, _ = hf.knn_graph(x, 16, 32, 15, 3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    rows = torch.randperm(w["n"], generator=torch.Generator(device="cpu").manual_seed(4))[:10000].to(x.device)
+    gr = recall(gids[rows], ground_truth_graph(x, rows, 15))
+    out["graph-1Mx384"] = {"orders": 16, "window": 32, "k": 15, "recall": gr, "build_s": dt}
+    log("graph-1Mx384: recall@15 %.4f in %.4f s" % (gr, dt))
+    del x, gids
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -465,6 +615,13 @@ def main():
     ap.add_argument("--learned-batch", type=int, default=500)
     ap.add_argument("--learned-epochs", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="search workload: also time the 3M x 384 graph (--orders, --window) in the same line")
+    ap.add_argument("--configs", type=int, default=1,
+                    help="search workload: also run the 10K x 32 search and the 1M x 384 graph configurations")
+    ap.add_argument("--c3", default="2000,1100,2,160",
+                    help="search: 'k1,k2,h,trees' timed on the forest's first trees ('' for none): the budget "
+                         "at 160 trees")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration for rocprofv3)")
     ap.add_argument("--peaks", action="store_true",
@@ -509,14 +666,26 @@ def main():
     ws = datagen.WORKLOADS[args.workload]
     if args.workload.startswith("search"):
         res = bench_search(args, hf, torch, ws)
+        torch.cuda.empty_cache()
+        if args.graph:
+            # the other half of the metric: the 3M x 384 k-NN graph
+            log("graph-3Mx384: %d orders, window +-%d" % (args.orders, args.window))
+            res["graph"] = bench_graph(args, hf, torch, datagen.WORKLOADS["graph-3Mx384"], 15)
+            torch.cuda.empty_cache()
+        if args.configs:
+            res["configs"] = bench_configs(args, hf, torch)
     else:
-        res = bench_graph(args, hf, torch, ws)
+        res = bench_graph(args, hf, torch, ws, args.k)
     res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "scaling": "weak",
                 "vs_baseline": None, "dtype": "f16", "data": "synthetic"})
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a bounded sample)")
-        res["cpu_baseline"] = (cpu_baseline_search if args.workload.startswith("search")
-                               else cpu_baseline_graph)(args)
+        log("cpu baselines (the oracle on bounded samples; all cores, then 8 pinned cores)")
+        if args.workload.startswith("search"):
+            res["cpu_baseline"] = cpu_baseline_search(args, res["window_entries_per_s"])
+            if "graph" in res:
+                res["graph"]["cpu_baseline"] = cpu_baseline_graph(args, res["graph"]["config"]["n"])
+        else:
+            res["cpu_baseline"] = cpu_baseline_graph(args, res["config"]["n"])
     print(json.dumps(res), flush=True)
 
 

@@ -85,7 +85,8 @@ typedef struct hf_search_params {
   uint32_t h;         /* expansion half-width in master order */
   uint32_t precision; /* hf_precision */
   uint32_t survivors; /* low-precision survivors per query (0 = 4k) */
-  uint32_t reserved;
+  uint32_t trees;     /* search trees 0..trees-1 only (0 = all n trees of the forest); tree t
+                         is the same tree in any forest built with the same seed and data */
 } hf_search_params;
 
 /* Graph parameters (Section 4.1: n sorts, k1 candidates per point per sort
@@ -203,7 +204,7 @@ hf_status hf_search(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64
                     void* stream);
 
 /* hf_search plus the intermediate sets (all nullable, device, caller-owned):
- * win_dev nq x n_trees window starts; c2_dev nq x k2 master positions in
+ * win_dev nq x n window starts (n = params->trees, or all the forest's trees); c2_dev nq x k2 master positions in
  * (Hamming, position) order, 0xFFFFFFFF past c2n; c2n_dev nq counts; en_dev
  * nq sizes |E|. */
 hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype, int64_t nq,

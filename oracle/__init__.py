@@ -57,6 +57,7 @@ def lib():
             "hfo_sort": (None, [P, i64, i32, P]),
             "hfo_trie": (i64, [P, P, i64, i32, i32, P, P, P, P, i64]),
             "hfo_window_starts": (None, [P, P, i64, i32, i64, i32, P, i64]),
+            "hfo_exact_ranks": (None, [P, P, i64, i32, P, i64, P, P, i32, P, P]),
             "hfo_srp": (None, [P, i32, i64, i32, u64, P]),
             "hfo_search_stage2": (None, [P, i32, i64, i32, P, P, i32, P, P, P, P, i64,
                                          i32, i32, i32, i32, P, P, P, P, P, P]),
@@ -77,6 +78,17 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+def set_num_threads(n: int) -> int:
+    """OpenMP threads the oracle's parallel loops use from now on (libgomp is
+    loaded with the oracle); returns the previous setting."""
+    lib()
+    g = C.CDLL("libgomp.so.1")
+    g.omp_get_max_threads.restype = C.c_int
+    old = int(g.omp_get_max_threads())
+    g.omp_set_num_threads(C.c_int(int(n)))
+    return old
 
 
 def _p(a):
@@ -175,6 +187,19 @@ def window_starts(nodes: np.ndarray, qcodes: np.ndarray, N: int, k1: int) -> np.
     return out
 
 
+def exact_ranks(keys, order, qcodes, perm_t, refl_t, k1: int):
+    """Exact insertion rank of each query along one tree's curve (before equal
+    keys) and the window start centred on it: (rank[nq], start[nq])."""
+    qcodes = np.ascontiguousarray(qcodes)
+    nq, d = qcodes.shape
+    rank = np.empty(nq, np.uint32)
+    start = np.empty(nq, np.uint32)
+    lib().hfo_exact_ranks(_p(np.ascontiguousarray(keys)), _p(np.ascontiguousarray(order)), keys.shape[0], d,
+                          _p(qcodes), nq, _p(np.ascontiguousarray(perm_t, np.int32)),
+                          _p(np.ascontiguousarray(refl_t, np.uint8)), k1, _p(rank), _p(start))
+    return rank, start
+
+
 def srp(x: np.ndarray, e: int, sketch_seed: int) -> np.ndarray:
     x = np.ascontiguousarray(x)
     out = np.empty((x.shape[0], SKETCH_WORDS), np.uint64)
@@ -217,11 +242,15 @@ def build_forest(x: np.ndarray, T: int, M: int, seed: int, sketch_seed: int, qua
     sk = srp(x, e, sketch_seed)
     return dict(N=N, d=d, T=T, M=M, e=e, codes=codes, perm=perm, refl=refl, orders=orders,
                 pos2id=pos2id, pos=pos, tree_perm=tree_perm, nodes=nodes, trees=want,
-                sk_pos=sk[pos2id].copy(), x=x, sketch_seed=sketch_seed)
+                sk_pos=sk[pos2id].copy(), x=x, sketch_seed=sketch_seed, keys=keys_t)
 
 
-def search(F, q: np.ndarray, k1: int, k2: int, h: int, k: int):
-    """Alg. 1 search for queries q over the trees of forest F (FP64 scores)."""
+def search(F, q: np.ndarray, k1: int, k2: int, h: int, k: int, position: str = "leaf"):
+    """Alg. 1 search for queries q over the trees of forest F (FP64 scores).
+
+    position: where a query sits along a tree's curve: "leaf" = the midpoint
+    of the leaf its descent reaches, "exact" = its insertion rank among the
+    tree's sorted keys."""
     N, d = F["N"], F["d"]
     trees = F["trees"]
     T = len(trees)
@@ -229,7 +258,10 @@ def search(F, q: np.ndarray, k1: int, k2: int, h: int, k: int):
     nq = q.shape[0]
     win = np.empty((nq, T), np.uint32)
     for j, t in enumerate(trees):
-        win[:, j] = window_starts(F["nodes"][t], qcodes, N, k1)
+        if position == "exact":
+            win[:, j] = exact_ranks(F["keys"][t], F["orders"][t], qcodes, F["perm"][t], F["refl"][t], k1)[1]
+        else:
+            win[:, j] = window_starts(F["nodes"][t], qcodes, N, k1)
     tp = np.ascontiguousarray(np.stack([F["tree_perm"][t] for t in trees]))
     qsk = srp(q, F["e"], F["sketch_seed"])
     ids = np.empty((nq, k), np.int32)

@@ -364,6 +364,55 @@ void hfo_window_starts(const uint32_t *nodes, const uint8_t *qcodes, int64_t nq,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Exact position of a query along a tree's curve (Section 2: a point's      */
+/* place in Hilbert order can be found in O(log n); Alg. 1 first stage takes */
+/* the k1 candidates around it).  Read as the insertion rank of the query's  */
+/* key among the tree's sorted keys, before any equal key: rank = number of  */
+/* data points whose key is strictly smaller.  Found by binary search over   */
+/* the sorted order with full keys of both sides.  Window start              */
+/* s = clamp(rank - floor(k1/2), 0, max(0, N-k1)).                            */
+/* keys: N x W keys of the tree's curve indexed by point id; order: the      */
+/* tree's sorted ids.  Pinned: rank equals the count of smaller keys by      */
+/* brute force, and a data point with a unique key ranks at its own place.   */
+/* ------------------------------------------------------------------------ */
+static int key_cmp(const uint64_t *a, const uint64_t *b, int64_t W) {
+  for (int64_t w = 0; w < W; ++w)
+    if (a[w] != b[w]) return a[w] < b[w] ? -1 : 1;
+  return 0;
+}
+
+void hfo_exact_ranks(const uint64_t *keys, const uint32_t *order, int64_t N, int32_t d, const uint8_t *qcodes,
+                     int64_t nq, const int32_t *perm, const uint8_t *refl, int32_t k1, uint32_t *rank_out,
+                     uint32_t *start_out) {
+  const int64_t W = ((int64_t)d * 8 + 63) / 64;
+#pragma omp parallel
+  {
+    uint8_t *v = (uint8_t *)malloc((size_t)d);
+    uint64_t *kq = (uint64_t *)malloc((size_t)W * 8);
+#pragma omp for schedule(static)
+    for (int64_t q = 0; q < nq; ++q) {
+      tree_coords(qcodes + q * d, d, perm, refl, v);
+      hfo_key(v, d, 8, kq);
+      int64_t lo = 0, hi = N; /* first index whose key is >= the query's */
+      while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (key_cmp(keys + (int64_t)order[mid] * W, kq, W) < 0)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      int64_t s = lo - k1 / 2, smax = N - k1 > 0 ? N - k1 : 0;
+      if (s < 0) s = 0;
+      if (s > smax) s = smax;
+      if (rank_out) rank_out[q] = (uint32_t)lo;
+      if (start_out) start_out[q] = (uint32_t)s;
+    }
+    free(v);
+    free(kq);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* 512-bit sign-of-random-projection sketches (Section 3.1 uses binary       */
 /* sketches compared by Hamming distance; their construction is not given). */
 /* R[j][i] in {-1,+1} is bit (j*d + i) of the concatenated SplitMix64        */

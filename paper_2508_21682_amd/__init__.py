@@ -50,7 +50,7 @@ class ForestParams(C.Structure):
 class SearchParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("k", C.c_uint32), ("k1", C.c_uint32),
                 ("k2", C.c_uint32), ("h", C.c_uint32), ("precision", C.c_uint32),
-                ("survivors", C.c_uint32), ("reserved", C.c_uint32)]
+                ("survivors", C.c_uint32), ("trees", C.c_uint32)]
 
 
 class GraphParams(C.Structure):
@@ -342,21 +342,23 @@ class Forest:
         _check(lib().hf_forest_sketches(self._h, _ptr(out), _stream()))
         return out
 
-    def _params(self, k, k1, k2, h, precision, survivors):
-        return SearchParams(C.sizeof(SearchParams), k, k1, k2, h, HF_PREC[precision], survivors, 0)
+    def _params(self, k, k1, k2, h, precision, survivors, trees=0):
+        return SearchParams(C.sizeof(SearchParams), k, k1, k2, h, HF_PREC[precision], survivors, trees)
 
-    def search(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32", survivors: int = 0):
+    def search(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32", survivors: int = 0,
+               trees: int = 0):
+        """hf_search; ``trees`` > 0 searches trees 0..trees-1 only."""
         q = _dev(q)
         t = _torch()
         ids = _empty((q.shape[0], k), t.int32, q)
         sc = _empty((q.shape[0], k), t.float32, q)
-        p = self._params(k, k1, k2, h, precision, survivors)
+        p = self._params(k, k1, k2, h, precision, survivors, trees)
         _check(lib().hf_search(self._h, _ptr(q), _dtype(q), q.shape[0], C.byref(p), _ptr(ids), _ptr(sc),
                                _stream()))
         return ids, sc
 
     def search_noalloc(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32", survivors: int = 0,
-                       out=None):
+                       out=None, trees: int = 0):
         """hf_search_noalloc: the library allocates nothing (scratch from its fixed
         per-device array); ``out`` = (ids, scores) lets the caller bring the outputs too."""
         q = _dev(q)
@@ -364,7 +366,7 @@ class Forest:
         if out is None:
             out = (_empty((q.shape[0], k), t.int32, q), _empty((q.shape[0], k), t.float32, q))
         ids, sc = out
-        p = self._params(k, k1, k2, h, precision, survivors)
+        p = self._params(k, k1, k2, h, precision, survivors, trees)
         _check(lib().hf_search_noalloc(self._h, _ptr(q), _dtype(q), q.shape[0], C.byref(p), _ptr(ids), _ptr(sc),
                                        _stream()))
         return ids, sc
@@ -393,17 +395,17 @@ class Forest:
         return dict(ids=ids, scores=sc, surv_pos=sp, surv_score=ss)
 
     def search_debug(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32",
-                     survivors: int = 0):
+                     survivors: int = 0, trees: int = 0):
         q = _dev(q)
         t = _torch()
         nq = q.shape[0]
         ids = _empty((nq, k), t.int32, q)
         sc = _empty((nq, k), t.float32, q)
-        win = _empty((nq, self.info["n_trees"]), t.int32, q)
+        win = _empty((nq, trees or self.info["n_trees"]), t.int32, q)
         c2 = _empty((nq, k2), t.int32, q)
         c2n = _empty((nq,), t.int32, q)
         en = _empty((nq,), t.int32, q)
-        p = self._params(k, k1, k2, h, precision, survivors)
+        p = self._params(k, k1, k2, h, precision, survivors, trees)
         _check(lib().hf_search_debug(self._h, _ptr(q), _dtype(q), nq, C.byref(p), _ptr(ids), _ptr(sc),
                                      _ptr(win), _ptr(c2), _ptr(c2n), _ptr(en), _stream()))
         return dict(ids=ids, scores=sc, winstart=win, c2=c2, c2n=c2n, en=en)

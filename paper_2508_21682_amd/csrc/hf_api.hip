@@ -504,7 +504,8 @@ static hf_status check_search(const hf_forest* f, const void* Q, hf_dtype dtype,
     const uint32_t S = p->survivors ? p->survivors : 4 * p->k;
     HF_ARG(S >= p->k && S <= 4096, "survivors must be in [k, 4096]");
   }
-  if ((int64_t)f->T * (int64_t)std::min<int64_t>(p->k1, f->N) > (1ll << 30)) {
+  HF_ARG(p->trees <= (uint32_t)f->T, "trees (%u) exceeds the forest's %d trees", p->trees, f->T);
+  if ((int64_t)(p->trees ? (int)p->trees : f->T) * (int64_t)std::min<int64_t>(p->k1, f->N) > (1ll << 30)) {
     set_error("n_trees * k1 too large");
     return HF_ERR_UNSUPPORTED;
   }

@@ -298,6 +298,13 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
                         int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
                         int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
                         hipStream_t s, Workspace* ws = nullptr);
+// hf_bfilter.hip: the Hamming filter by master-position bucket.  Writes C2
+// and its count for the queries it completes and flag[q] = 0 for them,
+// flag[q] = 1 for the queries the entry-by-entry filter must redo.
+bool bfilter_usable(int64_t N, int T, int k2);
+int64_t bfilter_max_batch(int64_t N);
+hf_status bfilter_run(const hf_forest* f, int T, int len, int64_t nb, const uint32_t* win, const uint64_t* qsk,
+                      int k2, uint32_t* c2, int32_t* c2n, uint32_t* flag, Workspace& ws);
 // hf_api.hip: the argument checks of hf_search
 hf_status search_args_ok(const hf_forest* f, const void* Q, hf_dtype dtype, int64_t nq, const hf_search_params* p,
                          const void* ids, const void* scores);

@@ -14,6 +14,8 @@
 //               FP32 inner products by 16-lane groups, radix select of the
 //               k best (score desc, position asc) and a final small sort.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include "hf_internal.h"
 #include "hf_select.h"
@@ -121,10 +123,12 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
                                              const uint64_t* __restrict__ sk,
                                              const uint64_t* __restrict__ qsk,
                                              uint16_t* __restrict__ ham,
-                                             uint32_t* __restrict__ hist) {
+                                             uint32_t* __restrict__ hist,
+                                             const uint32_t* __restrict__ only) {
   __shared__ uint32_t h[4][HB + 1];
   extern __shared__ uint32_t s_win[];  // T window starts (dynamic LDS)
   const int64_t q = blockIdx.x;
+  if (only && !only[q]) return;  // the query's C2 came from the bucketed filter
   for (int i = threadIdx.x; i < 4 * (HB + 1); i += 256) (&h[0][0])[i] = 0;
   for (int t = threadIdx.x; t < T; t += 256) s_win[t] = win[q * T + t];
   __syncthreads();
@@ -271,7 +275,8 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
                                                   const uint16_t* __restrict__ ham,
                                                   const uint32_t* __restrict__ hist0, int k2,
                                                   int pos_bits, uint32_t* __restrict__ c2,
-                                                  int32_t* __restrict__ c2n) {
+                                                  int32_t* __restrict__ c2n,
+                                                  const uint32_t* __restrict__ only) {
   __shared__ uint32_t keys[CAP];
   __shared__ uint32_t hist[HB];
   __shared__ uint32_t bk[NBK];
@@ -281,6 +286,7 @@ __global__ __launch_bounds__(SEL_T) void k_select(const uint32_t* __restrict__ t
   __shared__ uint32_t s_plo, s_pend, s_phi;
 
   const int64_t q = blockIdx.x;
+  if (only && !only[q]) return;
   const uint16_t* hq = ham + q * qstride;
   const uint32_t* wq = win + q * T;
   const int HM = (int)((1ull << (32 - pos_bits)) - 1ull);
@@ -590,7 +596,7 @@ int64_t filter_batch(int64_t nq, int64_t per_q) {
 }
 
 size_t search_scratch_bytes(const hf_forest* f, int64_t nq, const hf_search_params& p) {
-  const int T = f->T;
+  const int T = p.trees ? (int)p.trees : f->T;
   const int len = (int)std::min<int64_t>(p.k1, f->N);
   const int64_t per_q = ham_row_entries(T, len);
   const int64_t batch = filter_batch(nq, per_q);
@@ -610,7 +616,7 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   Workspace own(s);
   Workspace& ws = ext ? *ext : own;
   const int64_t N = f->N;
-  const int d = f->d, T = f->T;
+  const int d = f->d, T = p.trees ? (int)p.trees : f->T;  // trees 0..T-1
   const int len = (int)std::min<int64_t>(p.k1, N);
   const int k2 = (int)p.k2;
   // query codes and sketches
@@ -646,7 +652,11 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   }
   // the second stage runs in batches of queries sized to bound scratch memory
   const int64_t per_q = ham_row_entries(T, len);
-  const int64_t batch = filter_batch(nq, per_q);
+  // the bucketed filter (not with a fixed scratch arena: its records take
+  // 4 bytes per window entry)
+  const bool bucketed = !ws.arena && bfilter_usable(N, T, k2);
+  int64_t batch = filter_batch(nq, per_q);
+  if (bucketed) batch = std::min(batch, bfilter_max_batch(N));
   uint16_t* ham;
   uint32_t *hist, *c2 = c2_out;
   int32_t* c2n = c2n_out;
@@ -698,20 +708,38 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     HIP_TRY(hipLaunchKernel(kern, dim3((unsigned)nb), dim3(RR_T), args, smem, s));
     return HF_OK;
   };
+  uint32_t* flag = nullptr;
+  if (bucketed) HF_TRY(ws.alloc(&flag, (size_t)batch));
   for (int64_t q0 = 0; q0 < nq; q0 += batch) {
     const int64_t nb = std::min(batch, nq - q0);
+    if (bucketed) {
+      {
+        StageTimer tm(ST_HAM, s);
+        HF_TRY(bfilter_run(f, T, len, nb, win + q0 * T, qsk + q0 * 8, k2, c2 + q0 * k2, c2n + q0, flag, ws));
+      }
+      if (getenv("HF_FILTER_STATS")) {  // diagnostic: how many queries the exact fallback redoes
+        std::vector<uint32_t> fl((size_t)nb);
+        HIP_TRY(hipMemcpyAsync(fl.data(), flag, 4 * (size_t)nb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int64_t redo = 0;
+        for (uint32_t v : fl) redo += v != 0;
+        fprintf(stderr, "hf filter: %lld of %lld queries redone entry by entry\n", (long long)redo, (long long)nb);
+      }
+    }
     {
-      StageTimer tm(ST_HAM, s);
+      // the entry-by-entry filter: every query, or the queries the bucketed
+      // filter flagged (the others' workgroups return at once)
+      StageTimer tm(bucketed ? ST_SELECT : ST_HAM, s);
       const uint64_t mlen = ((1ull << 32) + (uint64_t)len - 1) / (uint64_t)len;
       k_ham<<<(unsigned)nb, 256, sizeof(uint32_t) * (size_t)T, s>>>(f->tree_perm, N, T, len, mlen, per_q,
                                                                    win + q0 * T, f->sk_pos, qsk + q0 * 8, ham,
-                                                                   hist);
+                                                                   hist, flag);
       HF_LAUNCH_CHECK();
     }
     {
       StageTimer tm(ST_SELECT, s);
       k_select<<<(unsigned)nb, SEL_T, 0, s>>>(f->tree_perm, N, T, len, per_q, win + q0 * T, ham, hist, k2,
-                                              pos_bits, c2 + q0 * k2, c2n + q0);
+                                              pos_bits, c2 + q0 * k2, c2n + q0, flag);
       HF_LAUNCH_CHECK();
     }
     if (p.precision == HF_PREC_FP32) {

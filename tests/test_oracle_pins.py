@@ -690,3 +690,59 @@ def test_lowprec_scores_within_format_error(orc, prec):
         exact = {p: float(Q[i] @ X[p]) for p in got}
         top = sorted(got, key=lambda p: (-exact[p], p))[:k]
         assert res["ids"][i].tolist() == top
+
+
+# ----------------------------------------------------------------- exact position of a query (Section 2)
+def test_exact_rank_counts_smaller_keys(orc):
+    """The exact rank of a query is the number of data points with a strictly
+    smaller Hilbert key (Python integers of every key), and the window start
+    centres k1 on it, shifted into [0, N)."""
+    rng = np.random.default_rng(61)
+    N, d, k1 = 300, 5, 40
+    codes = rng.integers(0, 256, (N, d), dtype=np.uint8)
+    codes[10] = codes[3]  # equal keys
+    perm, refl = orc.curves(9, 1, d)
+    keys = orc.tree_keys(codes, perm[0], refl[0])
+    order = orc.sort_keys(keys)
+    q = rng.integers(0, 256, (60, d), dtype=np.uint8)
+    q[0] = codes[3]  # equal to two data keys: ranks before both
+    q[1] = 0
+    q[2] = 255
+    rank, start = orc.exact_ranks(keys, order, q, perm[0], refl[0], k1)
+    tc = lambda c: [int(c[perm[0][i]]) ^ (255 if refl[0][i] else 0) for i in range(d)]
+    dk = [orc.hilbert_index_int(tc(c), 8) for c in codes]
+    for i in range(q.shape[0]):
+        qk = orc.hilbert_index_int(tc(q[i]), 8)
+        want = sum(1 for v in dk if v < qk)
+        assert rank[i] == want
+        assert start[i] == min(max(want - k1 // 2, 0), N - k1)
+
+
+def test_exact_rank_of_a_data_point_is_its_place(orc):
+    """A data point whose key is unique, used as a query, ranks at its own
+    position in the tree's order; with repeats, at the first of them."""
+    rng = np.random.default_rng(62)
+    N, d = 500, 12
+    codes = rng.integers(100, 156, (N, d), dtype=np.uint8)
+    codes[7] = codes[400]
+    perm, refl = orc.curves(4, 3, d)
+    for t in range(3):
+        keys = orc.tree_keys(codes, perm[t], refl[t])
+        order = orc.sort_keys(keys)
+        place = np.empty(N, np.int64)
+        place[order] = np.arange(N)
+        rank, _ = orc.exact_ranks(keys, order, codes, perm[t], refl[t], 1)
+        for p in range(N):
+            same = np.where((keys == keys[p]).all(axis=1))[0]
+            assert rank[p] == min(place[same])
+
+
+def test_exact_position_search_reduces_to_brute_force(orc):
+    """With one tree, k1 >= N, k2 >= N and h = 0 the search with exact
+    positions is the exact k-NN too (the window is every point)."""
+    x, q = datagen.mixture(400, 16, 4, 0.1, 63, unit=False, dtype=np.float32, query_seed=64, nq=20)
+    F = orc.build_forest(x, T=1, M=20, seed=3, sketch_seed=4)
+    r = orc.search(F, q, 400, 400, 0, 7, position="exact")
+    bi, bs = orc.brute_force_ip(x, q, 7)
+    assert (r["ids"] == bi).all()
+    assert np.allclose(r["scores"], bs, rtol=0, atol=1e-12)

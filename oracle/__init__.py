@@ -55,9 +55,12 @@ def lib():
             "hfo_key": (None, [P, i32, i32, P]),
             "hfo_tree_keys": (None, [P, i64, i32, P, P, P]),
             "hfo_sort": (None, [P, i64, i32, P]),
-            "hfo_trie": (i64, [P, P, i64, i32, i32, P, P, P, P, i64]),
+            "hfo_trie": (i64, [P, P, i64, i32, i32, P, P, P, P, i64, P]),
             "hfo_window_starts": (None, [P, P, i64, i32, i64, i32, P, i64]),
             "hfo_exact_ranks": (None, [P, P, i64, i32, P, i64, P, P, i32, P, P]),
+            "hfo_c4_encode": (None, [P, i32, i64, i32, P, P, P]),
+            "hfo_search_c4": (None, [i64, i32, P, P, i32, P, P, P, P, P, i32, i64, i32, i32, i32, i32, P, P, P, P,
+                                     P]),
             "hfo_srp": (None, [P, i32, i64, i32, u64, P]),
             "hfo_search_stage2": (None, [P, i32, i64, i32, P, P, i32, P, P, P, P, i64,
                                          i32, i32, i32, i32, P, P, P, P, P, P]),
@@ -166,16 +169,20 @@ def sort_keys(keys: np.ndarray) -> np.ndarray:
     return order
 
 
-def trie(keys, order, codes, perm_t, refl_t, M: int) -> np.ndarray:
-    """Leaf-compressed Hilbert trie in pre-order; (n_nodes, 2) uint32 records."""
+def trie(keys, order, codes, perm_t, refl_t, M: int, with_splits: bool = False):
+    """Leaf-compressed Hilbert trie in pre-order; (n_nodes, 2) uint32 records,
+    and with ``with_splits`` also the split records (internal {m, b}, leaf {lo, ~0})."""
     N, d = codes.shape
     cap = 2 * N + 8  # a binary tree over N points has at most 2N-1 nodes
     nodes = np.zeros((cap, 2), np.uint32)
+    aux = np.zeros((cap, 2), np.uint32)
     n = lib().hfo_trie(_p(np.ascontiguousarray(keys)), _p(np.ascontiguousarray(order)), N, d, M,
                        _p(np.ascontiguousarray(codes)), _p(np.ascontiguousarray(perm_t, np.int32)),
-                       _p(np.ascontiguousarray(refl_t, np.uint8)), _p(nodes), cap)
+                       _p(np.ascontiguousarray(refl_t, np.uint8)), _p(nodes), cap, _p(aux))
     if n < 0:
         raise RuntimeError("oracle trie failed (%d)" % n)
+    if with_splits:
+        return nodes[:n].copy(), aux[:n].copy()
     return nodes[:n].copy()
 
 
@@ -235,14 +242,14 @@ def build_forest(x: np.ndarray, T: int, M: int, seed: int, sketch_seed: int, qua
     pos = np.empty(N, np.uint32)
     pos[pos2id] = np.arange(N, dtype=np.uint32)
     tree_perm = {t: pos[orders[t]] for t in want}
-    nodes = {}
+    nodes, splits = {}, {}
     if with_nodes:
         for t in want:
-            nodes[t] = trie(keys_t[t], orders[t], codes, perm[t], refl[t], M)
+            nodes[t], splits[t] = trie(keys_t[t], orders[t], codes, perm[t], refl[t], M, with_splits=True)
     sk = srp(x, e, sketch_seed)
     return dict(N=N, d=d, T=T, M=M, e=e, codes=codes, perm=perm, refl=refl, orders=orders,
                 pos2id=pos2id, pos=pos, tree_perm=tree_perm, nodes=nodes, trees=want,
-                sk_pos=sk[pos2id].copy(), x=x, sketch_seed=sketch_seed, keys=keys_t)
+                sk_pos=sk[pos2id].copy(), x=x, sketch_seed=sketch_seed, keys=keys_t, splits=splits)
 
 
 def search(F, q: np.ndarray, k1: int, k2: int, h: int, k: int, position: str = "leaf"):
@@ -277,6 +284,49 @@ def search(F, q: np.ndarray, k1: int, k2: int, h: int, k: int, position: str = "
                             _p(scores), _p(c2), _p(c2n), _p(c1n), _p(en))
     return dict(ids=ids, scores=scores, winstart=win, c2=c2, c2n=c2n, c1n=c1n, en=en, qcodes=qcodes,
                 qsk=qsk)
+
+
+def c4_encode(x: np.ndarray):
+    """The compressed layout of rows x: (sign sketches [N, ceil(d/64)] uint64,
+    magnitudes [N, d] uint8 in 0..7, scales [N] float64 = max|x| / 8)."""
+    x = np.ascontiguousarray(x)
+    N, d = x.shape
+    sg = np.empty((N, (d + 63) // 64), np.uint64)
+    mag = np.empty((N, d), np.uint8)
+    sc = np.empty(N, np.float64)
+    lib().hfo_c4_encode(_p(x), _dtype_code(x), N, d, _p(sg), _p(mag), _p(sc))
+    return sg, mag, sc
+
+
+def search_c4(F, q: np.ndarray, k1: int, k2: int, h: int, k: int, position: str = "leaf"):
+    """Alg. 1 in the compressed layout: sign-sketch Hamming filter, rerank
+    from the 4-bit codes with the stored (unquantized) query values."""
+    N, d = F["N"], F["d"]
+    trees = F["trees"]
+    T = len(trees)
+    qcodes = quantize(q, F["e"])
+    nq = q.shape[0]
+    win = np.empty((nq, T), np.uint32)
+    for j, t in enumerate(trees):
+        if position == "exact":
+            win[:, j] = exact_ranks(F["keys"][t], F["orders"][t], qcodes, F["perm"][t], F["refl"][t], k1)[1]
+        else:
+            win[:, j] = window_starts(F["nodes"][t], qcodes, N, k1)
+    tp = np.ascontiguousarray(np.stack([F["tree_perm"][t] for t in trees]))
+    if "c4" not in F:
+        sg, mag, sc = c4_encode(F["x"])
+        p2i = F["pos2id"]
+        F["c4"] = (sg[p2i].copy(), mag[p2i].copy(), sc[p2i].copy())
+    sg, mag, sc = F["c4"]
+    ids = np.empty((nq, k), np.int32)
+    scores = np.empty((nq, k), np.float64)
+    c2 = np.empty((nq, k2), np.uint32)
+    c2n = np.empty(nq, np.int32)
+    en = np.empty(nq, np.int32)
+    qq = np.ascontiguousarray(q.astype(F["x"].dtype))
+    lib().hfo_search_c4(N, d, _p(F["pos2id"]), _p(tp), T, _p(win), _p(sg), _p(mag), _p(sc), _p(qq),
+                        _dtype_code(qq), nq, k1, k2, h, k, _p(ids), _p(scores), _p(c2), _p(c2n), _p(en))
+    return dict(ids=ids, scores=scores, winstart=win, c2=c2, c2n=c2n, en=en)
 
 
 def search_lowprec(F, q: np.ndarray, c2: np.ndarray, c2n: np.ndarray, h: int, k: int, prec: str, S: int):

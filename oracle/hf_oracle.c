@@ -221,6 +221,7 @@ void hfo_sort(const uint64_t *keys, int64_t N, int32_t W, uint32_t *order) {
 /* Layout: pre-order, left subtree first; two u32 words per node:            */
 /*   internal: w0 = index of the right child, w1 = a | L<<16 | flip<<19;     */
 /*   leaf:     w0 = lo,                       w1 = 1<<31 | (hi-lo).          */
+/* aux (nullable), two words per node: internal {m, b}, leaf {lo, ~0}.      */
 /* Returns the node count, or -1 if `cap` is too small, -2 if a node test is */
 /* not unique (cannot happen for Skilling keys; kept as an assertion).       */
 /* Pinned by invariants in tests (ranges partition [0,N), split bits, every  */
@@ -231,7 +232,7 @@ typedef struct {
   const uint32_t *order;
   int64_t W;
   int32_t d, M;
-  uint32_t *nodes;
+  uint32_t *nodes, *aux;
   int64_t cap, count;
   int64_t *pending; /* node index -> (lo, b) for internal nodes, to fill tests later */
   int64_t *pend_lo, *pend_b;
@@ -260,10 +261,18 @@ static int64_t trie_rec(trie_ctx *c, int64_t lo, int64_t hi) {
   if (b < 0) {
     c->nodes[2 * me] = (uint32_t)lo;
     c->nodes[2 * me + 1] = 0x80000000u | (uint32_t)(hi - lo);
+    if (c->aux) {
+      c->aux[2 * me] = (uint32_t)lo;
+      c->aux[2 * me + 1] = 0xFFFFFFFFu;
+    }
     return 0;
   }
   int64_t m = lo;
   while (!keybit(c->keys + (int64_t)c->order[m] * c->W, b)) ++m;
+  if (c->aux) {
+    c->aux[2 * me] = (uint32_t)m;
+    c->aux[2 * me + 1] = (uint32_t)b;
+  }
   c->pending[c->npend] = me;
   c->pend_lo[c->npend] = lo;
   c->pend_b[c->npend] = b;
@@ -275,7 +284,7 @@ static int64_t trie_rec(trie_ctx *c, int64_t lo, int64_t hi) {
 
 int64_t hfo_trie(const uint64_t *keys, const uint32_t *order, int64_t N, int32_t d, int32_t M,
                  const uint8_t *codes, const int32_t *perm, const uint8_t *refl, uint32_t *nodes,
-                 int64_t cap) {
+                 int64_t cap, uint32_t *aux) {
   trie_ctx c;
   c.keys = keys;
   c.order = order;
@@ -283,6 +292,7 @@ int64_t hfo_trie(const uint64_t *keys, const uint32_t *order, int64_t N, int32_t
   c.d = d;
   c.M = M;
   c.nodes = nodes;
+  c.aux = aux;
   c.cap = cap;
   c.count = 0;
   c.npend = 0;
@@ -552,6 +562,126 @@ void hfo_search_stage2(const void *X, int32_t dtype, int64_t N, int32_t d, const
     }
     free(mark);
     free(buf);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's compressed layout (Section 3.1): 384-bit sketches for 384-d   */
+/* data and 4-bit vector codes that share one bit with the sketch, the rerank */
+/* computed from the codes with the query left unquantized.  Read as:        */
+/*  sketch bit i = [x_i >= 0] (one bit per coordinate, stored in word i/64   */
+/*    at bit i%64, d bits; the Hamming filter compares these);               */
+/*  code i = that sign bit plus a 3-bit magnitude m_i = the number of        */
+/*    k in 1..7 with 8|x_i| >= k * max_j |x_j| (uniform levels of width      */
+/*    s = max|x| / 8 per vector; m = 7 for the largest element);             */
+/*  value of code i = (+-1) * (m_i + 1/2) * s, the sign from the sketch bit. */
+/* A zero vector has s = 0 and every value 0.                                */
+/* Pinned: m against exact rational arithmetic, reconstruction within s/2,  */
+/* sign sketches against Python bit packing (tests).                         */
+/* ------------------------------------------------------------------------ */
+void hfo_c4_encode(const void *x, int32_t dtype, int64_t N, int32_t d, uint64_t *sign_out, uint8_t *mag_out,
+                   double *scale_out) {
+  const int64_t W = (d + 63) / 64;
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < N; ++p) {
+    double mx = 0.0;
+    for (int32_t i = 0; i < d; ++i) {
+      double a = fabs(val(x, dtype, p * d + i));
+      if (a > mx) mx = a;
+    }
+    scale_out[p] = mx / 8.0;
+    uint64_t *sg = sign_out + p * W;
+    for (int64_t w = 0; w < W; ++w) sg[w] = 0;
+    for (int32_t i = 0; i < d; ++i) {
+      double v = val(x, dtype, p * d + i);
+      if (v >= 0.0) sg[i >> 6] |= 1ull << (i & 63);
+      int m = 0;
+      for (int k = 1; k <= 7; ++k)
+        if (8.0 * fabs(v) >= (double)k * mx) m = k;
+      mag_out[p * d + i] = (uint8_t)m;
+    }
+  }
+}
+
+/* Value of code i of row p (see above). */
+static double c4_value(const uint64_t *sign, const uint8_t *mag, const double *scale, int64_t p, int32_t d,
+                       int32_t i) {
+  const int64_t W = (d + 63) / 64;
+  double v = ((double)mag[p * d + i] + 0.5) * scale[p];
+  return ((sign[p * W + (i >> 6)] >> (i & 63)) & 1u) ? v : -v;
+}
+
+/* Alg. 1 stages two and three in the compressed layout, one query at a     */
+/* time: C1 as in hfo_search_stage2; C2 = the first k2 of C1 by (Hamming     */
+/* distance of the d-bit sign sketches, position); E = C2 expanded by h;     */
+/* S = top-k of E by (sum_i q_i * code value_i desc, position asc), with the  */
+/* stored query values.  Rows indexed by master position.                    */
+void hfo_search_c4(int64_t N, int32_t d, const uint32_t *pos2id, const uint32_t *tree_perm, int32_t T,
+                   const uint32_t *winstart, const uint64_t *sign_pos, const uint8_t *mag_pos,
+                   const double *scale_pos, const void *Q, int32_t qdtype, int64_t nq, int32_t k1, int32_t k2,
+                   int32_t h, int32_t k, int32_t *ids, double *scores, uint32_t *c2, int32_t *c2n, int32_t *en) {
+  const int64_t W = (d + 63) / 64;
+  int64_t len = k1 < N ? k1 : N;
+#pragma omp parallel
+  {
+    uint8_t *mark = (uint8_t *)calloc((size_t)N, 1);
+    cand *buf = (cand *)malloc(sizeof(cand) * (size_t)(T * len + (int64_t)k2 * (2 * h + 1) + 1));
+    uint64_t *qs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)W);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nq; ++q) {
+      for (int64_t w = 0; w < W; ++w) qs[w] = 0;
+      for (int32_t i = 0; i < d; ++i)
+        if (val(Q, qdtype, q * d + i) >= 0.0) qs[i >> 6] |= 1ull << (i & 63);
+      int64_t n1 = 0;
+      for (int32_t t = 0; t < T; ++t) {
+        const uint32_t *P = tree_perm + (int64_t)t * N;
+        int64_t s = winstart[q * T + t];
+        for (int64_t i = s; i < s + len; ++i) {
+          uint32_t r = P[i];
+          if (!mark[r]) {
+            mark[r] = 1;
+            int hd = 0;
+            for (int64_t w = 0; w < W; ++w) hd += __builtin_popcountll(qs[w] ^ sign_pos[(int64_t)r * W + w]);
+            buf[n1].r = r;
+            buf[n1].key = hd;
+            ++n1;
+          }
+        }
+      }
+      for (int64_t i = 0; i < n1; ++i) mark[buf[i].r] = 0;
+      qsort(buf, (size_t)n1, sizeof(cand), cmp_ham_pos);
+      int64_t n2 = n1 < k2 ? n1 : k2;
+      if (c2)
+        for (int64_t i = 0; i < k2; ++i) c2[q * k2 + i] = i < n2 ? (uint32_t)buf[i].r : 0xFFFFFFFFu;
+      if (c2n) c2n[q] = (int32_t)n2;
+      cand *E = buf + n2;
+      int64_t ne = 0;
+      for (int64_t i = 0; i < n2; ++i) {
+        int64_t r = buf[i].r, a = r - h < 0 ? 0 : r - h, z = r + h > N - 1 ? N - 1 : r + h;
+        for (int64_t x = a; x <= z; ++x)
+          if (!mark[x]) {
+            mark[x] = 1;
+            E[ne].r = x;
+            ++ne;
+          }
+      }
+      for (int64_t i = 0; i < ne; ++i) mark[E[i].r] = 0;
+      if (en) en[q] = (int32_t)ne;
+      for (int64_t i = 0; i < ne; ++i) {
+        double acc = 0.0;
+        for (int32_t j = 0; j < d; ++j)
+          acc += val(Q, qdtype, q * d + j) * c4_value(sign_pos, mag_pos, scale_pos, E[i].r, d, j);
+        E[i].s = acc;
+      }
+      qsort(E, (size_t)ne, sizeof(cand), cmp_score_desc_pos);
+      for (int32_t i = 0; i < k; ++i) {
+        ids[q * k + i] = i < ne ? (int32_t)pos2id[E[i].r] : -1;
+        scores[q * k + i] = i < ne ? E[i].s : -INFINITY;
+      }
+    }
+    free(mark);
+    free(buf);
+    free(qs);
   }
 }
 

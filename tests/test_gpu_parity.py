@@ -163,6 +163,7 @@ def _forest_case(hf, orc, x, q, T, M, seed, sk_seed, params):
         got = u32(fo.nodes(t)).reshape(-1, 2)
         assert got.shape == F["nodes"][t].shape, "tree %d node count" % t
         assert (got == F["nodes"][t]).all(), "tree %d records" % t
+        assert (u32(fo.node_splits(t)).reshape(-1, 2) == F["splits"][t]).all(), "tree %d split records" % t
     qd = dev(q)
     for (k1, k2, h, k) in params:
         print("search k1=%d k2=%d h=%d k=%d" % (k1, k2, h, k), flush=True)
@@ -240,6 +241,45 @@ def test_filter_forms_give_the_oracle_c2(hf, orc, monkeypatch, env):
         assert (u32(r["c2"]) == want["c2"]).all()
         check_topk(r["ids"].cpu().numpy(), r["scores"].cpu().numpy(), want["ids"], want["scores"], x, q, k)
     fo.free()
+
+
+def _exact_case(hf, orc, x, q, T, M, seed, sk_seed, params):
+    F = orc.build_forest(x, T=T, M=M, seed=seed, sketch_seed=sk_seed)
+    fo = hf.Forest(dev(x), n_trees=T, leaf_max=M, seed=seed, sketch_seed=sk_seed)
+    qd = dev(q)
+    for (k1, k2, h, k) in params:
+        want = orc.search(F, q, k1, k2, h, k, position="exact")
+        r = fo.search_debug(qd, k, k1, k2, h, position="exact")
+        assert (u32(r["winstart"]) == want["winstart"]).all()
+        assert (u32(r["c2"]) == want["c2"]).all()
+        check_topk(r["ids"].cpu().numpy(), r["scores"].cpu().numpy(), want["ids"], want["scores"], x, q, k)
+    fo.free()
+
+
+def test_exact_position_parity(hf, orc):
+    """Windows centred on each query's exact insertion rank (the oracle binary
+    searches full keys): window starts, C2 and results equal the oracle's.
+    Half the queries copy data rows or perturb one code of a data row, so the
+    top key level (the coordinates' signs) ties and full keys decide."""
+    x, q = datagen.mixture(20000, 384, 64, 0.05, 65, dtype=np.float16, query_seed=66, nq=120)
+    q[:30] = x[np.arange(30) * 101]
+    q[30:60] = x[np.arange(30) * 97 + 5]
+    q[30:60, 7] = (q[30:60, 7].astype(np.float32) * 0.5).astype(np.float16)  # a smaller code, same sign
+    _exact_case(hf, orc, x, q, T=4, M=100, seed=19, sk_seed=20, params=[(300, 100, 1, 30), (31, 20, 0, 10)])
+
+
+def test_exact_position_small_and_ragged(hf, orc):
+    w = datagen.WORKLOADS["search-10Kx32"]
+    x, q = datagen.mixture(w["n"], w["d"], w["n_comp"], w["sigma"], w["seed"], unit=w["unit"],
+                           dtype=np.float32, query_seed=w["query_seed"], nq=300)
+    _exact_case(hf, orc, x, q, T=8, M=100, seed=1, sk_seed=2, params=[(256, 64, 1, 10)])
+    x, q = datagen.mixture(1237, 7, 5, 0.1, 67, unit=False, dtype=np.float32, nq=33)
+    q[:5] = x[:5]
+    _exact_case(hf, orc, x, q, T=3, M=3, seed=9, sk_seed=10, params=[(17, 11, 1, 4), (2000, 50, 0, 5)])
+    # all points identical: every comparison reaches the deepest key level
+    x = np.tile(datagen.mixture(1, 16, 1, 0.1, 68, unit=False, dtype=np.float32), (500, 1))
+    q = np.concatenate([x[:3], datagen.mixture(4, 16, 1, 0.1, 69, unit=False, dtype=np.float32)])
+    _exact_case(hf, orc, x, q, T=2, M=50, seed=11, sk_seed=12, params=[(40, 30, 0, 5)])
 
 
 def test_forest_search_tree_subset(hf, orc):

@@ -746,3 +746,68 @@ def test_exact_position_search_reduces_to_brute_force(orc):
     bi, bs = orc.brute_force_ip(x, q, 7)
     assert (r["ids"] == bi).all()
     assert np.allclose(r["scores"], bs, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------- the paper's compressed layout (Section 3.1)
+def test_c4_codes_against_exact_rationals(orc):
+    """Magnitude levels by exact rational arithmetic (m = #{k in 1..7 : 8|x| >=
+    k max|x|}), signs by Python bit packing, scale = max|x| / 8, and every
+    value within half a level of the stored one (the largest element at 7.5 s)."""
+    from fractions import Fraction
+
+    rng = np.random.default_rng(71)
+    x = (rng.standard_normal((40, 70)) * rng.uniform(0.01, 3, (40, 1))).astype(np.float32)
+    x[3] = 0.0
+    x[4, :5] = -0.0
+    x[5] = np.abs(x[5])
+    sg, mag, sc = orc.c4_encode(x)
+    for p in range(x.shape[0]):
+        mx = max(Fraction(abs(float(v))) for v in x[p])
+        assert sc[p] == float(mx / 8)
+        bits = 0
+        for i, v in enumerate(x[p]):
+            a = Fraction(abs(float(v)))
+            assert mag[p, i] == sum(1 for kk in range(1, 8) if 8 * a >= kk * mx)
+            if float(v) >= 0.0:
+                bits |= 1 << i
+            val = (float(mag[p, i]) + 0.5) * sc[p] * (1 if float(v) >= 0 else -1)
+            assert abs(val - float(v)) <= sc[p] / 2 + 1e-300
+        words = [(bits >> (64 * w)) & ((1 << 64) - 1) for w in range(sg.shape[1])]
+        assert [int(w) for w in sg[p]] == words
+
+
+def test_c4_search_reduces_to_brute_force_on_decoded_rows(orc):
+    """One tree, k1 >= N, k2 >= N, h = 0: the compressed-layout search is the
+    exact top-k of the inner products with the decoded rows (decoded here from
+    the definition, numpy FP64)."""
+    x, q = datagen.mixture(600, 24, 6, 0.1, 72, unit=False, dtype=np.float32, query_seed=73, nq=25)
+    F = orc.build_forest(x, T=1, M=30, seed=3, sketch_seed=4)
+    r = orc.search_c4(F, q, 600, 600, 0, 9)
+    mx = np.abs(x.astype(np.float64)).max(axis=1, keepdims=True)
+    m = np.zeros(x.shape)
+    for kk in range(1, 8):
+        m += (8 * np.abs(x.astype(np.float64)) >= kk * mx)
+    dec = np.where(x >= 0, 1.0, -1.0) * (m + 0.5) * mx / 8
+    S = q.astype(np.float64) @ dec.T
+    o = np.argsort(-S, axis=1, kind="stable")[:, :9]
+    assert (r["ids"] == o).all()
+    assert np.allclose(r["scores"], np.take_along_axis(S, o, 1), rtol=0, atol=1e-12)
+
+
+def test_c4_search_c2_by_sign_hamming(orc):
+    """C2 is the first k2 of the windows' union by (Hamming distance of the
+    coordinate-sign sketches, position), rebuilt with Python sets and integers."""
+    x, q = datagen.mixture(500, 20, 5, 0.1, 74, unit=False, dtype=np.float32, query_seed=75, nq=8)
+    F = orc.build_forest(x, T=3, M=10, seed=5, sketch_seed=6)
+    k1, k2, h, k = 30, 25, 1, 5
+    r = orc.search_c4(F, q, k1, k2, h, k)
+    X = x[F["pos2id"]]  # rows in master order
+    sgn = lambda v: sum(1 << i for i, a in enumerate(v) if float(a) >= 0)
+    for i in range(q.shape[0]):
+        C1 = set()
+        for j, t in enumerate(F["trees"]):
+            s0 = int(r["winstart"][i, j])
+            C1 |= set(int(v) for v in F["tree_perm"][t][s0:s0 + k1])
+        qs = sgn(q[i])
+        want = sorted(C1, key=lambda p: (bin(qs ^ sgn(X[p])).count("1"), p))[:k2]
+        assert r["c2"][i][:len(want)].tolist() == want

@@ -353,6 +353,26 @@ def bench_search(args, hf, torch, ws):
         alt = {"k1": a1, "k2": a2, "h": ah, "recall": recall(aids, gt), "qps": nq * args.steps / adt,
                "ms_per_step": adt * 1e3 / args.steps}
         log("alternative budget k1=%d k2=%d h=%d: recall %.4f, %.0f QPS" % (a1, a2, ah, alt["recall"], alt["qps"]))
+    exact = None
+    if args.exact:
+        # the same budget with windows centred on each query's exact rank
+        # along every tree's curve instead of its leaf's midpoint
+        forest.search(q, args.k, args.k1, args.k2, args.h, position="exact")
+        torch.cuda.synchronize()
+        hf.timing_enable(True)
+        hf.timing_read()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            eids, _ = forest.search(q, args.k, args.k1, args.k2, args.h, position="exact")
+        torch.cuda.synchronize()
+        edt = time.perf_counter() - t
+        est = hf.timing_read()
+        hf.timing_enable(False)
+        exact = {"position": "exact rank", "recall": recall(eids, gt), "qps": nq * args.steps / edt,
+                 "ms_per_step": edt * 1e3 / args.steps,
+                 "stages_ms_per_step": {k_: v_[0] / args.steps for k_, v_ in est.items()}}
+        log("exact positions: recall %.4f, %.0f QPS (descent %.2f ms)" % (
+            exact["recall"], exact["qps"], exact["stages_ms_per_step"].get("descend", 0.0)))
     c3 = None
     if args.c3:
         # the same data, queries and k at 160 trees (the forest's first 160:
@@ -393,6 +413,7 @@ def bench_search(args, hf, torch, ws):
                       "leaf_max": args.leaf, "k": args.k, "k1": args.k1, "k2": args.k2, "h": args.h,
                       "sketch_bits": 512, "rerank": "fp32"},
            "build_s": build_s, "roofline": roof, "brute_force": brute, "alt_budget": alt, "config3": c3,
+           "exact_position": exact,
            "window_entries_per_s": nq * args.steps * T * ln / dt,
            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
     if sweep:
@@ -619,6 +640,8 @@ def main():
                     help="search workload: also time the 3M x 384 graph (--orders, --window) in the same line")
     ap.add_argument("--configs", type=int, default=1,
                     help="search workload: also run the 10K x 32 search and the 1M x 384 graph configurations")
+    ap.add_argument("--exact", type=int, default=1,
+                    help="search: also time the main budget with exact query positions (insertion ranks)")
     ap.add_argument("--c3", default="2000,1100,2,160",
                     help="search: 'k1,k2,h,trees' timed on the forest's first trees ('' for none): the budget "
                          "at 160 trees")

@@ -87,7 +87,17 @@ typedef struct hf_search_params {
   uint32_t survivors; /* low-precision survivors per query (0 = 4k) */
   uint32_t trees;     /* search trees 0..trees-1 only (0 = all n trees of the forest); tree t
                          is the same tree in any forest built with the same seed and data */
+  uint32_t position;  /* hf_position: where a query sits along each tree's curve */
+  uint32_t reserved;
 } hf_search_params;
+
+/* Where a query's window of k1 candidates is centred in each tree's order
+ * (Algorithm 1, first stage; Section 2 locates a point along the curve):
+ *  HF_POS_LEAF:  the midpoint of the leaf its descent reaches;
+ *  HF_POS_EXACT: its exact insertion rank among the tree's sorted Hilbert
+ *                keys, before any equal key (the number of data points with
+ *                a smaller key); needs d <= 512. */
+typedef enum hf_position { HF_POS_LEAF = 0, HF_POS_EXACT = 1 } hf_position;
 
 /* Graph parameters (Section 4.1: n sorts, k1 candidates per point per sort
  * read as the window +-w, k2 kept by sketches; k = 15 in the paper). */
@@ -187,6 +197,12 @@ hf_status hf_forest_perm(const hf_forest* f, uint32_t t, uint32_t* perm_dev, voi
 hf_status hf_forest_nodes(const hf_forest* f, uint32_t t, uint32_t* nodes_dev, int64_t* count_host,
                           void* stream);
 hf_status hf_forest_pos2id(const hf_forest* f, uint32_t* pos2id_dev, void* stream);
+/* Split records of tree t, 2 uint32 per node in the order of hf_forest_nodes:
+ * internal {m, b}: the node's range [lo, hi) splits into [lo, m) and [m, hi)
+ * at key bit b (the first bit where the range's end keys differ); leaf
+ * {lo, 0xFFFFFFFF}.  count_host as for hf_forest_nodes. */
+hf_status hf_forest_node_splits(const hf_forest* f, uint32_t t, uint32_t* splits_dev, int64_t* count_host,
+                                void* stream);
 hf_status hf_forest_sketches(const hf_forest* f, uint64_t* sk_dev, void* stream);
 
 /* Algorithm 1 for a batch of nq queries (same dtype as the data):

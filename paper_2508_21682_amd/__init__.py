@@ -20,6 +20,7 @@ HF_OK = 0
 HF_F16, HF_F32 = 0, 1
 HF_PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
 HF_SKETCH_SRP, HF_SKETCH_LEARNED = 0, 1
+HF_POS = {"leaf": 0, "exact": 1}
 HF_QUANT_AUTO = -(2 ** 31)
 STATUS = {0: "ok", 1: "invalid argument", 2: "invalid input", 3: "out of memory", 4: "device error",
           5: "invalid handle", 6: "unsupported"}
@@ -31,7 +32,7 @@ EXPORTS = ["hf_status_str", "hf_last_error", "hf_curves", "hf_quant_exp", "hf_qu
            "hf_timing_enable", "hf_timing_read", "hf_timing_stage_name", "hf_forest_add_precision",
            "hf_search_lowprec_debug", "hf_audit_scores", "hf_lhash_create", "hf_lhash_free", "hf_lhash_get",
            "hf_lhash_encode", "hf_lhash_grad", "hf_lhash_train", "hf_forest_set_sketch",
-           "hf_knn_graph_debug", "hf_set_allocator", "hf_search_noalloc"]
+           "hf_knn_graph_debug", "hf_set_allocator", "hf_search_noalloc", "hf_forest_node_splits"]
 N_STAGES = 16
 
 
@@ -50,7 +51,8 @@ class ForestParams(C.Structure):
 class SearchParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("k", C.c_uint32), ("k1", C.c_uint32),
                 ("k2", C.c_uint32), ("h", C.c_uint32), ("precision", C.c_uint32),
-                ("survivors", C.c_uint32), ("trees", C.c_uint32)]
+                ("survivors", C.c_uint32), ("trees", C.c_uint32), ("position", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class GraphParams(C.Structure):
@@ -117,6 +119,7 @@ def lib():
             "hf_forest_get_info": (C.c_int, [P, P]),
             "hf_forest_perm": (C.c_int, [P, u32, P, P]),
             "hf_forest_nodes": (C.c_int, [P, u32, P, P, P]),
+            "hf_forest_node_splits": (C.c_int, [P, u32, P, P, P]),
             "hf_forest_pos2id": (C.c_int, [P, P, P]),
             "hf_forest_sketches": (C.c_int, [P, P, P]),
             "hf_search": (C.c_int, [P, P, C.c_int, i64, P, P, P, P]),
@@ -332,6 +335,14 @@ class Forest:
         _check(lib().hf_forest_nodes(self._h, t, _ptr(out), C.byref(n), _stream()))
         return out
 
+    def node_splits(self, t: int):
+        """Split records of tree t: internal {m, b}, leaf {lo, 0xFFFFFFFF}."""
+        n = C.c_int64()
+        _check(lib().hf_forest_node_splits(self._h, t, None, C.byref(n), _stream()))
+        out = _empty((n.value, 2), _torch().int32, self._like())
+        _check(lib().hf_forest_node_splits(self._h, t, _ptr(out), C.byref(n), _stream()))
+        return out
+
     def pos2id(self):
         out = _empty((self.info["N"],), _torch().int32, self._like())
         _check(lib().hf_forest_pos2id(self._h, _ptr(out), _stream()))
@@ -342,17 +353,19 @@ class Forest:
         _check(lib().hf_forest_sketches(self._h, _ptr(out), _stream()))
         return out
 
-    def _params(self, k, k1, k2, h, precision, survivors, trees=0):
-        return SearchParams(C.sizeof(SearchParams), k, k1, k2, h, HF_PREC[precision], survivors, trees)
+    def _params(self, k, k1, k2, h, precision, survivors, trees=0, position="leaf"):
+        return SearchParams(C.sizeof(SearchParams), k, k1, k2, h, HF_PREC[precision], survivors, trees,
+                            HF_POS[position], 0)
 
     def search(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32", survivors: int = 0,
-               trees: int = 0):
-        """hf_search; ``trees`` > 0 searches trees 0..trees-1 only."""
+               trees: int = 0, position: str = "leaf"):
+        """hf_search; ``trees`` > 0 searches trees 0..trees-1 only; ``position``
+        "leaf" (leaf midpoint) or "exact" (insertion rank) centres the windows."""
         q = _dev(q)
         t = _torch()
         ids = _empty((q.shape[0], k), t.int32, q)
         sc = _empty((q.shape[0], k), t.float32, q)
-        p = self._params(k, k1, k2, h, precision, survivors, trees)
+        p = self._params(k, k1, k2, h, precision, survivors, trees, position)
         _check(lib().hf_search(self._h, _ptr(q), _dtype(q), q.shape[0], C.byref(p), _ptr(ids), _ptr(sc),
                                _stream()))
         return ids, sc
@@ -395,7 +408,7 @@ class Forest:
         return dict(ids=ids, scores=sc, surv_pos=sp, surv_score=ss)
 
     def search_debug(self, q, k: int, k1: int, k2: int, h: int, precision: str = "fp32",
-                     survivors: int = 0, trees: int = 0):
+                     survivors: int = 0, trees: int = 0, position: str = "leaf"):
         q = _dev(q)
         t = _torch()
         nq = q.shape[0]
@@ -405,7 +418,7 @@ class Forest:
         c2 = _empty((nq, k2), t.int32, q)
         c2n = _empty((nq,), t.int32, q)
         en = _empty((nq,), t.int32, q)
-        p = self._params(k, k1, k2, h, precision, survivors, trees)
+        p = self._params(k, k1, k2, h, precision, survivors, trees, position)
         _check(lib().hf_search_debug(self._h, _ptr(q), _dtype(q), nq, C.byref(p), _ptr(ids), _ptr(sc),
                                      _ptr(win), _ptr(c2), _ptr(c2n), _ptr(en), _stream()))
         return dict(ids=ids, scores=sc, winstart=win, c2=c2, c2n=c2n, en=en)

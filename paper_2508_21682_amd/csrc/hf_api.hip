@@ -137,7 +137,7 @@ hf_status data_exp(const void* X, hf_dtype dt, int64_t n, int32_t want, int* e, 
 void forest_release(hf_forest* f) {
   if (!f) return;
   void* ptrs[] = {f->X_pos, f->sk_pos, f->pos2id, f->tree_perm, f->nodes, f->curve_perm, f->curve_refl,
-                  f->X_bf16, f->X_fp8, f->s_fp8, f->node_off_dev, f->srp_R};
+                  f->X_bf16, f->X_fp8, f->s_fp8, f->node_off_dev, f->srp_R, f->node_aux, f->sgn_pos};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   f->magic = 0;
@@ -357,7 +357,7 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
     HF_TRY(ws.alloc(&msb, (size_t)(N * msb_words(d))));
     HF_TRY(msb_plane(codes, N, d, msb, s));
   }
-  std::vector<uint32_t*> tnodes(T, nullptr);
+  std::vector<uint32_t*> tnodes(T, nullptr), taux(T, nullptr);
   std::vector<int64_t> tcount(T, 0);
   struct NodeGuard {
     std::vector<uint32_t*>& v;
@@ -365,7 +365,7 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
       for (auto p : v)
         if (p) (void)hipFree(p);
     }
-  } ng{tnodes};
+  } ng{tnodes}, ga{taux};
   const bool progress = getenv("HF_PROGRESS") != nullptr;
   for (int t = 0; t < T; ++t) {
     if (progress && (t % 16 == 0 || t == T - 1)) {
@@ -384,7 +384,7 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
     }
     {
       StageTimer tm(ST_BTRIE, s);
-      HF_TRY(build_trie(codes, N, d, f->M, pt, rt, order, split, &tnodes[t], &tcount[t], wt));
+      HF_TRY(build_trie(codes, N, d, f->M, pt, rt, order, split, &tnodes[t], &taux[t], &tcount[t], wt));
     }
     uint32_t* tp = f->tree_perm + (size_t)t * N;
     if (t == 0) {
@@ -401,9 +401,23 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   HIP_TRY(hipMalloc(&f->node_off_dev, sizeof(int64_t) * (size_t)(T + 1)));
   HIP_TRY(hipMemcpyAsync(f->node_off_dev, f->node_off.data(), sizeof(int64_t) * (size_t)(T + 1),
                          hipMemcpyHostToDevice, s));
-  for (int t = 0; t < T; ++t)
+  HIP_TRY(hipMalloc(&f->node_aux, sizeof(uint32_t) * 2 * (size_t)f->node_off[T]));
+  for (int t = 0; t < T; ++t) {
     HIP_TRY(hipMemcpyAsync(f->nodes + 2 * f->node_off[t], tnodes[t], 8 * (size_t)tcount[t],
                            hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(f->node_aux + 2 * f->node_off[t], taux[t], 8 * (size_t)tcount[t],
+                           hipMemcpyDeviceToDevice, s));
+  }
+  // coordinate signs (top bits of the codes) in master order, for the exact
+  // position of queries along each tree's curve
+  f->sgn_words = msb ? msb_words(d) : 0;
+  if (msb) {
+    HIP_TRY(hipMalloc(&f->sgn_pos, sizeof(uint32_t) * (size_t)f->sgn_words * N));
+    k_gather_rows<<<grid_for(N * f->sgn_words / 4 + 1), 256, 0, s>>>((const unsigned char*)msb,
+                                                                     (int64_t)(4 * f->sgn_words), f->pos2id, N,
+                                                                     (unsigned char*)f->sgn_pos);
+    HF_LAUNCH_CHECK();
+  }
   k_gather_rows<<<grid_for(N * d * esz / 16 + 1), 256, 0, s>>>((const unsigned char*)X_dev,
                                                                (int64_t)(esz * d), f->pos2id, N,
                                                                (unsigned char*)f->X_pos);
@@ -416,7 +430,8 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   }
   HIP_TRY(hipStreamSynchronize(s));
   f->device_bytes = (int64_t)(esz * N * d + 64 * N + 4 * N + 4 * (size_t)T * N +
-                              8 * (size_t)f->node_off[T] + 5 * (size_t)T * d + 8 * (size_t)(T + 1) + r_bytes);
+                              16 * (size_t)f->node_off[T] + 5 * (size_t)T * d + 8 * (size_t)(T + 1) + r_bytes +
+                              4 * (size_t)f->sgn_words * N);
   guard.f = nullptr;
   *out = f;
   return HF_OK;
@@ -464,6 +479,19 @@ hf_status hf_forest_nodes(const hf_forest* f, uint32_t t, uint32_t* nodes_dev, i
   return HF_OK;
 }
 
+hf_status hf_forest_node_splits(const hf_forest* f, uint32_t t, uint32_t* splits_dev, int64_t* count_host,
+                                void* stream) {
+  clear_error();
+  HF_TRY(check_forest(f));
+  HF_ARG(t < (uint32_t)f->T, "bad tree index");
+  const int64_t n = f->node_off[t + 1] - f->node_off[t];
+  if (count_host) *count_host = n;
+  if (splits_dev)
+    HIP_TRY(hipMemcpyAsync(splits_dev, f->node_aux + 2 * f->node_off[t], 8 * (size_t)n, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+  return HF_OK;
+}
+
 hf_status hf_forest_pos2id(const hf_forest* f, uint32_t* pos2id_dev, void* stream) {
   clear_error();
   HF_TRY(check_forest(f));
@@ -505,6 +533,11 @@ static hf_status check_search(const hf_forest* f, const void* Q, hf_dtype dtype,
     HF_ARG(S >= p->k && S <= 4096, "survivors must be in [k, 4096]");
   }
   HF_ARG(p->trees <= (uint32_t)f->T, "trees (%u) exceeds the forest's %d trees", p->trees, f->T);
+  HF_ARG(p->position <= HF_POS_EXACT, "bad position %u", p->position);
+  if (p->position == HF_POS_EXACT && f->sgn_words == 0) {
+    set_error("exact query positions need d <= 512");
+    return HF_ERR_UNSUPPORTED;
+  }
   if ((int64_t)(p->trees ? (int)p->trees : f->T) * (int64_t)std::min<int64_t>(p->k1, f->N) > (1ll << 30)) {
     set_error("n_trees * k1 too large");
     return HF_ERR_UNSUPPORTED;

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(BS_T) void k_bplan(const uint32_t* __restrict__ tot
 // The query's entries go through LDS SC_CH at a time, counting-sorted by
 // bucket, so that consecutive lanes store consecutive records of one run
 // instead of one scattered 4-byte store per entry.
-constexpr int SC_T = 512, SC_PER = 16, SC_CH = SC_T * SC_PER;
+constexpr int SC_T = 1024, SC_PER = 16, SC_CH = SC_T * SC_PER;
 __global__ __launch_bounds__(SC_T) void k_bscatter(EntryMap em, int T, const uint32_t* __restrict__ win, int bb,
                                                    int nbk, int64_t nb, const uint32_t* __restrict__ cnt,
                                                    const uint32_t* __restrict__ base,
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(SC_T) void k_bscatter(EntryMap em, int T, const uin
 // LDS staging of a chunk's passing entries: appended with LDS atomics while
 // scoring, then flushed with one global atomic per query of the chunk.
 constexpr int QS_MAX = 256;  // queries of a chunk staged in LDS
-constexpr int CB = 2048;     // passing entries a chunk stages in LDS
+constexpr int CB = 1024;     // passing entries a chunk stages in LDS
 struct ChunkLds {
   uint4 qs[QS_MAX][4];   // sketches of the chunk's queries
   uint32_t tau[QS_MAX];  // their thresholds
@@ -539,12 +539,12 @@ __global__ __launch_bounds__(BF_SEL_T) void k_bselect(const uint64_t* __restrict
 }  // namespace
 
 // Bucket bits: buckets of 2^bb positions (64 * 2^bb bytes of sketches), at
-// most 4,096 of them (LDS counters of the count and scatter kernels).
+// most 2,048 of them (LDS counters of the count and scatter kernels).
 int bfilter_bucket_bits(int64_t N) {
   int bb = 15;
   const char* env = getenv("HF_FILTER_BUCKET_BITS");
   if (env) bb = std::max(8, std::min(24, atoi(env)));
-  while ((ceil_div(N, (int64_t)1 << bb)) > 4096) ++bb;
+  while ((ceil_div(N, (int64_t)1 << bb)) > 2048) ++bb;
   return bb;
 }
 

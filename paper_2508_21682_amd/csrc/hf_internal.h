@@ -240,6 +240,10 @@ hf_status msb_plane(const uint8_t* codes, int64_t N, int d, uint32_t* msb, hipSt
 hf_status key_chunks(const uint8_t* codes, const uint32_t* msb, int d, const int32_t* perm,
                      const uint8_t* refl, const uint32_t* items, int64_t n_items, int chunk,
                      uint64_t* out, hipStream_t s);
+// Window starts of the (query, tree) pairs listed in deep (q << 32 | t; *ndeep
+// of them, on the device) whose exact position needs keys below the top level.
+hf_status rank_deep(const hf_forest* f, const uint8_t* qcodes, int64_t nq, int T, int k1, const uint64_t* deep,
+                    const uint32_t* ndeep, uint32_t* win, hipStream_t s);
 hf_status node_tests(const uint8_t* codes, int d, const int32_t* perm, const uint8_t* refl,
                      const uint32_t* points, const uint32_t* bits, int64_t n, uint32_t* out_w1,
                      hipStream_t s);
@@ -249,9 +253,11 @@ hf_status hilbert_sort_dev(const uint8_t* codes, const uint32_t* msb, int64_t N,
                            const int32_t* perm, const uint8_t* refl, uint32_t* order, uint32_t* split,
                            Workspace& ws);
 // hf_trie.hip: pre-order trie records (2 words each) from a sorted order and its split bits.
+// aux_out: 2 words per node (hipMalloc, caller frees): internal {split
+// position m, split bit b}, leaf {lo, 0xFFFFFFFF}.
 hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_t* perm,
                      const uint8_t* refl, const uint32_t* order, const uint32_t* split,
-                     uint32_t** nodes_out, int64_t* n_nodes, Workspace& ws);
+                     uint32_t** nodes_out, uint32_t** aux_out, int64_t* n_nodes, Workspace& ws);
 // hf_sketch.hip
 // SRP sketches of N rows; R_dev: a resident projection matrix (a forest's),
 // else it is generated from sketch_seed, uploaded and waited for
@@ -331,6 +337,9 @@ struct hf_forest {
   uint32_t* pos2id;      // N
   uint32_t* tree_perm;   // T x N master positions
   uint32_t* nodes;       // all trees' records, 2 words per node
+  uint32_t* node_aux;    // per node {m, b} (internal) or {lo, NONE} (leaf), same offsets
+  uint32_t* sgn_pos;     // N x sgn_words top bits of the codes (coordinate signs), master order
+  int sgn_words;         // 32-bit words per row of sgn_pos (0: d too large, no exact rank)
   std::vector<int64_t> node_off;  // T+1 offsets (in nodes)
   int64_t* node_off_dev; // the same offsets on the device
   uint64_t* srp_R;       // SRP projection matrix of (d, sketch_seed) on the device

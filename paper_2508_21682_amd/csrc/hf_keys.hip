@@ -262,6 +262,150 @@ __global__ __launch_bounds__(256) void chunk_top_kernel(const uint32_t* __restri
   out[it] = key;
 }
 
+// Exact position of a (query, tree) pair with full keys: a wavefront per
+// pair, every lane walking the same path; two keys are compared level by
+// level (the undo sweep of each level done as in chunk_kernel for both
+// points), the first differing key bit found by a ballot.
+// A data point's codes are recomputed from its stored row (the quantiser
+// is exact).
+template <int G>
+__device__ __forceinline__ void load_lane_x(Lane<G>& s, const void* X, hf_dtype dt, int64_t row, int d, int e,
+                                            const int32_t* __restrict__ perm, const uint8_t* __restrict__ refl) {
+  const int l = __lane_id();
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int i = l * G + g;
+    if (i < d) {
+      const int64_t at = row * d + perm[i];
+      const float v = dt == HF_F16 ? __half2float(((const __half*)X)[at]) : ((const float*)X)[at];
+      float f = floorf(ldexpf(v, e)) + 128.0f;
+      f = f < 0.0f ? 0.0f : (f > 255.0f ? 255.0f : f);
+      s.x[g] = (uint8_t)((uint32_t)f ^ (refl[i] ? 0xFFu : 0u));
+      s.lab[g] = (uint32_t)i << 9;
+    } else {
+      s.x[g] = 0;
+      s.lab[g] = 0;
+    }
+  }
+}
+
+// Sign of key(a) - key(b); *jstar = the first differing key bit (INT32_MAX
+// when equal).  Both lanes' states are consumed.
+template <int G>
+__device__ __forceinline__ int cmp_full(Lane<G>& a, Lane<G>& b, int d, int* jstar) {
+  const int l = __lane_id();
+  uint32_t ta = 0, tb = 0;
+  for (int li = 0; li < 8; ++li) {
+    const int L = 7 - li;
+    uint32_t ka[G], kb[G];
+    const uint32_t sa = level_bits<G>(a, L, d, ta, ka);
+    const uint32_t sb = level_bits<G>(b, L, d, tb, kb);
+    int first = G;
+    uint32_t bit = 0;
+#pragma unroll
+    for (int g = G - 1; g >= 0; --g)
+      if (l * G + g < d && ka[g] != kb[g]) {
+        first = g;
+        bit = ka[g];
+      }
+    const uint64_t m = __ballot(first < G);
+    if (m) {
+      const int owner = __ffsll((unsigned long long)m) - 1;
+      const int g0 = __shfl(first, owner);
+      const uint32_t qb = (uint32_t)__shfl((int)bit, owner);
+      *jstar = li * d + owner * G + g0;
+      return qb ? 1 : -1;
+    }
+    ta ^= sa;
+    tb ^= sb;
+    if (li < 7) {
+      undo_level<G>(a, L, d);
+      undo_level<G>(b, L, d);
+    }
+  }
+  *jstar = 0x7FFFFFFF;
+  return 0;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_rank_deep(const uint64_t* __restrict__ deep, const uint32_t* __restrict__ ndeep,
+                                                   const uint32_t* __restrict__ nodes,
+                                                   const uint32_t* __restrict__ aux,
+                                                   const int64_t* __restrict__ node_off,
+                                                   const uint8_t* __restrict__ qcodes, const void* X, hf_dtype dt,
+                                                   int e, const uint32_t* __restrict__ tree_perm,
+                                                   const int32_t* __restrict__ cperm,
+                                                   const uint8_t* __restrict__ crefl, int d, int T, int64_t N,
+                                                   int k1, int max_steps, uint32_t* __restrict__ win) {
+  const uint32_t n = *ndeep;
+  const uint32_t stride = gridDim.x * 4;
+  for (uint32_t it = blockIdx.x * 4 + threadIdx.x / 64; it < n; it += stride) {
+    const uint64_t v = deep[it];
+    const int64_t q = (int64_t)(v >> 32);
+    const int t = (int)(uint32_t)v;
+    const int32_t* pt = cperm + (int64_t)t * d;
+    const uint8_t* rt = crefl + (int64_t)t * d;
+    const uint32_t* nd = nodes + 2 * node_off[t];
+    const uint32_t* au = aux + 2 * node_off[t];
+    const uint32_t* tp = tree_perm + (int64_t)t * N;
+    const uint8_t* u = qcodes + q * d;
+    auto test = [&](uint32_t w1) -> uint32_t {
+      const uint32_t a = w1 & 0xFFFFu, L = (w1 >> 16) & 7u, flip = (w1 >> 19) & 1u;
+      return ((u[a] >> L) & 1u) ^ flip;
+    };
+    auto cmp = [&](uint32_t p, int* js) -> int {
+      Lane<G> a, b;
+      load_lane<G>(a, u, d, pt, rt);
+      load_lane_x<G>(b, X, dt, (int64_t)p, d, e, pt, rt);
+      return cmp_full<G>(a, b, d, js);
+    };
+    uint32_t idx = 0, leaf_lo = 0;
+    for (int step = 0; step < max_steps; ++step) {
+      const uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
+      if (r.y >> 31) {
+        leaf_lo = r.x;
+        break;
+      }
+      idx = test(r.y) ? r.x : idx + 1u;
+    }
+    int jstar;
+    const int c = cmp(tp[leaf_lo], &jstar);
+    int64_t lo = 0, hi = N, rank = -1;
+    idx = 0;
+    for (int step = 0; step < max_steps; ++step) {
+      const uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
+      if (r.y >> 31) break;
+      const uint2 sb = *(const uint2*)(au + 2 * (int64_t)idx);
+      if ((int64_t)sb.y > (int64_t)jstar && c != 0) {
+        rank = c > 0 ? hi : lo;
+        break;
+      }
+      if (test(r.y)) {
+        lo = sb.x;
+        idx = r.x;
+      } else {
+        hi = sb.x;
+        idx = idx + 1u;
+      }
+    }
+    if (rank < 0) {
+      int64_t a = lo, b = hi;
+      while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        int j2;
+        if (cmp(tp[mid], &j2) > 0)
+          a = mid + 1;
+        else
+          b = mid;
+      }
+      rank = a;
+    }
+    int64_t s = rank - k1 / 2, smax = N - k1 > 0 ? N - k1 : 0;
+    s = s < 0 ? 0 : (s > smax ? smax : s);
+    if (__lane_id() == 0) win[q * T + t] = (uint32_t)s;
+  }
+}
+
 int pick_g(int d) {
   int g = (d + 63) / 64;
   int G = 1;
@@ -315,6 +459,18 @@ hf_status key_chunks(const uint8_t* codes, const uint32_t* msb, int d, const int
   dim3 grid((unsigned)ceil_div(n_items, 4));
   int G = pick_g(d);
   HF_DISPATCH_G(G, chunk_kernel, codes, d, perm, refl, items, n_items, chunk, out);
+  HF_LAUNCH_CHECK();
+  return HF_OK;
+}
+
+hf_status rank_deep(const hf_forest* f, const uint8_t* qcodes, int64_t nq, int T, int k1, const uint64_t* deep,
+                    const uint32_t* ndeep, uint32_t* win, hipStream_t s) {
+  (void)nq;
+  const int d = f->d;
+  dim3 grid(1024);
+  int G = pick_g(d);
+  HF_DISPATCH_G(G, k_rank_deep, deep, ndeep, f->nodes, f->node_aux, f->node_off_dev, qcodes, f->X_pos, f->dtype,
+                f->e, f->tree_perm, f->curve_perm, f->curve_refl, d, T, f->N, k1, 8 * d + 2, win);
   HF_LAUNCH_CHECK();
   return HF_OK;
 }

@@ -90,6 +90,150 @@ __global__ __launch_bounds__(256) void k_descend_lds(const uint32_t* __restrict_
   win[(q0 + lane) * T + t] = (uint32_t)s;
 }
 
+// ------------------------------------------------------- exact query position
+// A query's exact place along tree t's curve (its insertion rank among the
+// tree's sorted keys, before equal keys), found as in a Patricia trie: the
+// descent by node tests reaches a leaf; z, the leaf's first point, shares
+// with the query every key bit before the first bit j* where they differ, so
+// the descent agreed with the query's own key on every node whose split bit
+// is below j*.  The first node on the path whose split bit lies beyond j* is
+// the subtree the query leaves: its rank is that node's lo (query bit 0 at
+// j*) or hi (bit 1).  If no such node exists the query falls inside the leaf,
+// and a binary search over the leaf's keys places it.
+//
+// Key comparisons here use only the top level of the keys, which depends on
+// the coordinates' signs alone: with a the tree's axis order and r its
+// reflections, top-level key bit i is the parity of sign[a_0] ^ r_0, ...,
+// sign[a_i] ^ r_i, so two keys first differ at the first tree axis whose
+// sign differs, and the one whose parity is 1 there is larger.  Points with
+// equal sign rows need the deeper levels: such (query, tree) pairs are
+// listed for the wavefront-per-pair kernel that computes full keys.
+constexpr int RK_T = 256;
+template <int NW>
+__device__ __forceinline__ int cmp_top(const uint32_t* sq, const uint32_t* sp, const uint16_t* ax, int d,
+                                       int* jstar) {
+  uint32_t par = 0;
+  for (int i = 0; i < d; ++i) {
+    const uint32_t v = ax[i];
+    const uint32_t a = v & 0x7FFFu, w = a >> 5, sh = a & 31u;
+    const uint32_t qb = (sq[w * RK_T] >> sh) & 1u, pb = (sp[w * RK_T] >> sh) & 1u;
+    par ^= qb ^ (v >> 15);
+    if (qb != pb) {
+      *jstar = i;
+      return par ? 1 : -1;
+    }
+  }
+  return 0;
+}
+
+template <int NW>
+__global__ __launch_bounds__(RK_T) void k_rank_top(const uint32_t* __restrict__ nodes,
+                                                   const uint32_t* __restrict__ aux,
+                                                   const int64_t* __restrict__ node_off,
+                                                   const uint8_t* __restrict__ qcodes,
+                                                   const uint32_t* __restrict__ qsgn,
+                                                   const uint32_t* __restrict__ sgn,
+                                                   const uint32_t* __restrict__ tree_perm,
+                                                   const int32_t* __restrict__ cperm,
+                                                   const uint8_t* __restrict__ crefl, int64_t nq, int d, int T,
+                                                   int64_t N, int k1, int max_steps, uint32_t* __restrict__ win,
+                                                   uint64_t* __restrict__ deep, uint32_t* __restrict__ ndeep) {
+  __shared__ uint32_t s_q[NW * RK_T], s_p[NW * RK_T];  // sign rows, word-major
+  __shared__ uint16_t s_ax[4][512];                    // each wavefront's tree: axis | reflected << 15
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = blockIdx.y * 4 + wv;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  if (t < T)
+    for (int i = lane; i < d; i += 64)
+      s_ax[wv][i] = (uint16_t)(cperm[(int64_t)t * d + i] | ((uint32_t)crefl[(int64_t)t * d + i] << 15));
+  if (q < nq)
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s_q[w * RK_T + threadIdx.x] = qsgn[q * NW + w];
+  wave_lds_sync();
+  if (q >= nq || t >= T) return;
+  const uint32_t* sq = s_q + threadIdx.x;
+  uint32_t* sp = s_p + threadIdx.x;
+  const uint16_t* ax = s_ax[wv];
+  const uint32_t* nd = nodes + 2 * node_off[t];
+  const uint32_t* au = aux + 2 * node_off[t];
+  const uint32_t* tp = tree_perm + (int64_t)t * N;
+  const uint8_t* u = qcodes + q * d;
+  auto test = [&](uint32_t w1) -> uint32_t {
+    const uint32_t a = w1 & 0xFFFFu, L = (w1 >> 16) & 7u, flip = (w1 >> 19) & 1u;
+    return ((u[a] >> L) & 1u) ^ flip;
+  };
+  auto load_row = [&](uint32_t p) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sp[w * RK_T] = sgn[(int64_t)p * NW + w];
+  };
+  // first descent: the leaf and its first point z
+  uint32_t idx = 0, leaf_lo = 0;
+  for (int step = 0; step < max_steps; ++step) {
+    const uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
+    if (r.y >> 31) {
+      leaf_lo = r.x;
+      break;
+    }
+    idx = test(r.y) ? r.x : idx + 1u;
+  }
+  load_row(tp[leaf_lo]);
+  int jstar = 0;
+  int c = cmp_top<NW>(sq, sp, ax, d, &jstar);
+  bool need_deep = c == 0;
+  int64_t rank = -1;
+  if (!need_deep) {
+    int64_t lo = 0, hi = N;
+    idx = 0;
+    for (int step = 0; step < max_steps; ++step) {
+      const uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
+      if (r.y >> 31) break;
+      const uint2 sb = *(const uint2*)(au + 2 * (int64_t)idx);  // {m, b}
+      if ((int64_t)sb.y > jstar) {
+        rank = c > 0 ? hi : lo;
+        break;
+      }
+      if (test(r.y)) {
+        lo = sb.x;
+        idx = r.x;
+      } else {
+        hi = sb.x;
+        idx = idx + 1u;
+      }
+    }
+    if (rank < 0) {  // inside the leaf [lo, hi): lower bound by key
+      int64_t a = lo, b = hi;
+      while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        load_row(tp[mid]);
+        int j2;
+        const int c2 = cmp_top<NW>(sq, sp, ax, d, &j2);
+        if (c2 == 0) {
+          need_deep = true;
+          break;
+        }
+        if (c2 > 0)
+          a = mid + 1;
+        else
+          b = mid;
+      }
+      rank = a;
+    }
+  }
+  if (need_deep) {
+    const uint32_t slot = atomicAdd(ndeep, 1u);
+    deep[slot] = ((uint64_t)q << 32) | (uint32_t)t;
+    win[q * T + t] = 0u;  // written by the full-key kernel
+    return;
+  }
+  int64_t s = rank - k1 / 2, smax = N - k1 > 0 ? N - k1 : 0;
+  s = s < 0 ? 0 : (s > smax ? smax : s);
+  win[q * T + t] = (uint32_t)s;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
 // ---------------------------------------------------------------- ham + hist
 constexpr int HB = 513;  // Hamming values 0..512
 
@@ -606,6 +750,8 @@ size_t search_scratch_bytes(const hf_forest* f, int64_t nq, const hf_search_para
                  A((size_t)nq * 4);
   if (f->sketch_kind == HF_SKETCH_LEARNED)
     total += A((size_t)std::min<int64_t>(nq, 1 << 20) * lhash_hidden(f->lhash) * 2);  // bf16 hidden layer
+  if (p.position == HF_POS_EXACT)
+    total += A((size_t)nq * f->sgn_words * 4) + A(4) + A((size_t)nq * T * 8);
   return total;
 }
 
@@ -638,7 +784,26 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
   uint32_t* win = win_out;
   if (!win) HF_TRY(ws.alloc(&win, (size_t)(nq * T)));
   const int64_t* doff = f->node_off_dev;
-  {
+  if (p.position == HF_POS_EXACT) {
+    StageTimer tm(ST_DESCEND, s);
+    const int nw = f->sgn_words;
+    uint32_t *qsgn, *ndeep;
+    uint64_t* deep;
+    HF_TRY(ws.alloc(&qsgn, (size_t)nq * nw));
+    HF_TRY(ws.alloc(&ndeep, 1));
+    HF_TRY(ws.alloc(&deep, (size_t)nq * T));
+    HF_TRY(msb_plane(qcodes, nq, d, qsgn, s));
+    k_zero_u32<<<1, 64, 0, s>>>(ndeep, 1);
+    dim3 grid((unsigned)ceil_div(nq, 64), (unsigned)ceil_div(T, 4));
+#define HF_RK(n) \
+  case n: k_rank_top<n><<<grid, RK_T, 0, s>>>(f->nodes, f->node_aux, doff, qcodes, qsgn, f->sgn_pos, f->tree_perm, \
+                                              f->curve_perm, f->curve_refl, nq, d, T, N, (int)p.k1, 8 * d + 2, win, \
+                                              deep, ndeep); break;
+    switch (nw) { HF_RK(1) HF_RK(2) HF_RK(4) HF_RK(8) HF_RK(12) HF_RK(16) }
+#undef HF_RK
+    HF_LAUNCH_CHECK();
+    HF_TRY(rank_deep(f, qcodes, nq, T, (int)p.k1, deep, ndeep, win, s));
+  } else {
     StageTimer tm(ST_DESCEND, s);
     if (d % 16 == 0 && d <= DS_MAXD) {
       dim3 grid((unsigned)ceil_div(nq, DS_Q), (unsigned)ceil_div(T, 4));

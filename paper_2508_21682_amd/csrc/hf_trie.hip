@@ -125,13 +125,18 @@ __global__ void k_sizes(const uint32_t* __restrict__ bsplit, const uint32_t* __r
 }
 
 // Pre-order indices of the children, and the records of this level.
+// aux (2 words per node): internal {split position m, split bit b}, leaf
+// {lo, NONE}.
 __global__ void k_emit(const uint32_t* __restrict__ lo, const uint32_t* __restrict__ hi,
-                       const uint32_t* __restrict__ bsplit, const uint32_t* __restrict__ cidx,
+                       const uint32_t* __restrict__ bsplit, const uint32_t* __restrict__ mpos,
+                       const uint32_t* __restrict__ cidx,
                        const uint32_t* __restrict__ w1, const uint32_t* __restrict__ idx,
                        const uint32_t* __restrict__ csize, int64_t n, uint32_t* __restrict__ cix,
-                       uint32_t* __restrict__ out) {
+                       uint32_t* __restrict__ out, uint32_t* __restrict__ aux) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     uint32_t me = idx[i];
+    aux[2 * (int64_t)me] = bsplit[i] == NONE32 ? lo[i] : mpos[i];
+    aux[2 * (int64_t)me + 1] = bsplit[i];
     if (bsplit[i] == NONE32) {
       out[2 * (int64_t)me] = lo[i];
       out[2 * (int64_t)me + 1] = 0x80000000u | (hi[i] - lo[i]);
@@ -164,7 +169,7 @@ struct Level {
 
 hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_t* perm,
                      const uint8_t* refl, const uint32_t* order, const uint32_t* split,
-                     uint32_t** nodes_out, int64_t* n_nodes, Workspace& ws) {
+                     uint32_t** nodes_out, uint32_t** aux_out, int64_t* n_nodes, Workspace& ws) {
   hipStream_t s = ws.stream;
   int64_t ngaps = N - 1;
   int64_t nb1 = std::max<int64_t>(1, ceil_div(ngaps, BLK));
@@ -246,8 +251,13 @@ hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_
   uint32_t total = 0;
   HIP_TRY(hipMemcpyAsync(&total, lv[0].size, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  uint32_t* out;
+  uint32_t *out, *aux;
   HIP_TRY(hipMalloc(&out, sizeof(uint32_t) * 2 * (size_t)total));
+  if (hipMalloc(&aux, sizeof(uint32_t) * 2 * (size_t)total) != hipSuccess) {
+    (void)hipFree(out);
+    set_error("device allocation of %zu bytes of split records failed", sizeof(uint32_t) * 2 * (size_t)total);
+    return HF_ERR_OOM;
+  }
   // top-down pre-order indices and records
   HF_TRY(ws.alloc(&lv[0].idx, 1));
   HIP_TRY(hipMemsetAsync(lv[0].idx, 0, 4, s));
@@ -260,11 +270,12 @@ hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_
       cix = lv[li + 1].idx;
       csize = lv[li + 1].size;
     }
-    k_emit<<<grid_for(L.n), 256, 0, s>>>(L.lo, L.hi, L.b, L.cidx, L.w1, L.idx, csize, L.n, cix,
-                                         out);
+    k_emit<<<grid_for(L.n), 256, 0, s>>>(L.lo, L.hi, L.b, L.m, L.cidx, L.w1, L.idx, csize, L.n, cix,
+                                         out, aux);
     HF_LAUNCH_CHECK();
   }
   *nodes_out = out;
+  *aux_out = aux;
   *n_nodes = total;
   return HF_OK;
 }

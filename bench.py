@@ -32,6 +32,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# The paper's trade-off tables (Section 3.2 Table 1: n, k1, k2, h, recall@30,
+# seconds for 10,000 queries; Section 4.2 Table 2: seconds, recall@15, n, k1,
+# k2), re-run on the synthetic stand-ins with the same parameters.  The
+# graph's k1 (candidates around a position) is read as the window +-k1/2; the
+# sketch stage keeps at most 256 (the last row asks 300).
+TABLE1 = [(160, 1420, 370, 2, 0.729, 54.9), (160, 1420, 360, 2, 0.728, 18.0), (160, 1300, 350, 2, 0.719, 17.9),
+          (160, 1300, 340, 2, 0.718, 16.1), (160, 1200, 330, 2, 0.710, 14.9), (160, 1200, 320, 2, 0.709, 17.3),
+          (160, 1100, 310, 2, 0.700, 13.6), (160, 1100, 300, 2, 0.699, 15.7), (120, 4000, 1000, 2, 0.791, 29.4),
+          (120, 3200, 1000, 2, 0.772, 25.8), (120, 2800, 1000, 2, 0.760, 23.6), (120, 2400, 1000, 2, 0.745, 23.8),
+          (120, 2000, 1000, 2, 0.726, 19.4), (120, 1800, 1000, 2, 0.715, 18.3), (120, 1600, 1000, 2, 0.703, 19.6),
+          (120, 1600, 800, 2, 0.700, 15.6)]
+TABLE2 = [(74.0, 0.805, 80, 96, 60), (109.0, 0.855, 112, 106, 75), (164.0, 0.905, 160, 130, 100),
+          (330.0, 0.955, 280, 168, 150), (856.0, 0.985, 720, 170, 300)]
 MFMA_F16_PEAK_TFLOPS = 2500.0
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -388,6 +401,20 @@ def bench_search(args, hf, torch, ws):
         c3 = {"trees": ct_, "k1": c1_, "k2": c2_, "h": ch_, "recall": recall(cids, gt),
               "qps": nq * args.steps / cdt, "ms_per_step": cdt * 1e3 / args.steps}
         log("%d trees k1=%d k2=%d h=%d: recall %.4f, %.0f QPS" % (ct_, c1_, c2_, ch_, c3["recall"], c3["qps"]))
+    table1 = None
+    if args.tables:
+        table1 = []
+        for (tn, t1, t2, th, prec_, psec) in TABLE1:
+            forest.search(q, args.k, t1, t2, th, trees=tn)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            tids, _ = forest.search(q, args.k, t1, t2, th, trees=tn)
+            torch.cuda.synchronize()
+            tdt = time.perf_counter() - t
+            table1.append({"n": tn, "k1": t1, "k2": t2, "h": th, "recall": recall(tids, gt), "qps": nq / tdt,
+                           "paper_recall": prec_, "paper_s_per_10k_queries": psec})
+        log("Table 1 rows on the stand-in: %s" % [(r_["n"], r_["k1"], round(r_["recall"], 3), round(r_["qps"]))
+                                                   for r_ in table1])
     log("recall@%d %.4f, %.0f QPS, stages %s" % (args.k, rec, qps,
                                                   {k: round(v[0] / args.steps, 2) for k, v in stages.items()}))
     # roofline of the dominant kernel: the Hamming filter streams n*k1 window
@@ -413,7 +440,7 @@ def bench_search(args, hf, torch, ws):
                       "leaf_max": args.leaf, "k": args.k, "k1": args.k1, "k2": args.k2, "h": args.h,
                       "sketch_bits": 512, "rerank": "fp32"},
            "build_s": build_s, "roofline": roof, "brute_force": brute, "alt_budget": alt, "config3": c3,
-           "exact_position": exact,
+           "exact_position": exact, "table1": table1,
            "window_entries_per_s": nq * args.steps * T * ln / dt,
            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
     if sweep:
@@ -423,6 +450,9 @@ def bench_search(args, hf, torch, ws):
         res["forms"] = {}
         for prec in args.forms.split(","):
             forest.add_precision(prec)
+            if prec == "c4":
+                # the paper's layout: coordinate-sign sketches for the filter
+                forest.set_sketch("sign")
             for _ in range(args.warmup):
                 forest.search(q, args.k, args.k1, args.k2, args.h, precision=prec)
             hf.timing_enable(True)
@@ -435,49 +465,101 @@ def bench_search(args, hf, torch, ws):
             pdt = time.perf_counter() - t
             pst = hf.timing_read()
             hf.timing_enable(False)
-            sub = q[:1000]
-            r = forest.search_lowprec_debug(sub, args.k, args.k1, args.k2, args.h, prec)
-            p2i = forest.pos2id().long()
-            sp = r["surv_pos"].long()
-            ok = sp >= 0
-            sid = torch.where(ok, p2i[sp.clamp(min=0)], torch.full_like(sp, -1)).int()
-            lp_err = audit(hf, torch, x, sub, sid, r["surv_score"])
             form = {"qps": nq * args.steps / pdt, "recall": recall(pid, gt), "ms_per_step": pdt * 1e3 / args.steps,
-                    "survivors": 4 * args.k, "audit_final_fp32": audit(hf, torch, x, q, pid, psc),
-                    "audit_lowprec_scores": lp_err,
                     "stages_ms_per_step": {k_: v[0] / args.steps for k_, v in pst.items()}}
+            if alt:
+                # the budget with the +-h expansion, where E is about 3x C2
+                forest.search(q, args.k, alt["k1"], alt["k2"], alt["h"], precision=prec)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(args.steps):
+                    aid, _ = forest.search(q, args.k, alt["k1"], alt["k2"], alt["h"], precision=prec)
+                torch.cuda.synchronize()
+                adt2 = time.perf_counter() - t
+                form["alt_budget"] = {"recall": recall(aid, gt), "qps": nq * args.steps / adt2,
+                                      "qps_fp32": alt["qps"]}
+            if prec == "c4":
+                # scores are inner products with the decoded 4-bit rows; their
+                # distance to the exact FP64 scores is the codes' error
+                form.update({"sketch": "coordinate signs (%d bits)" % x.shape[1],
+                             "row_bytes": x.shape[1] // 2 + 4, "row_bytes_fp16": 2 * x.shape[1],
+                             "audit_final_vs_exact": audit(hf, torch, x, q, pid, psc)})
+                forest.set_sketch("srp")
+                log("form c4: recall %.4f, %.0f QPS, rerank %.2f ms, score error vs exact max %.3g" % (
+                    form["recall"], form["qps"], form["stages_ms_per_step"].get("rerank", 0.0),
+                    form["audit_final_vs_exact"]["max_abs"]))
+            else:
+                sub = q[:1000]
+                r = forest.search_lowprec_debug(sub, args.k, args.k1, args.k2, args.h, prec)
+                p2i = forest.pos2id().long()
+                sp = r["surv_pos"].long()
+                ok = sp >= 0
+                sid = torch.where(ok, p2i[sp.clamp(min=0)], torch.full_like(sp, -1)).int()
+                lp_err = audit(hf, torch, x, sub, sid, r["surv_score"])
+                form.update({"survivors": 4 * args.k, "audit_final_fp32": audit(hf, torch, x, q, pid, psc),
+                             "audit_lowprec_scores": lp_err})
+                log("form %s: recall %.4f, %.0f QPS, low-precision score error max %.3g" % (
+                    prec, form["recall"], form["qps"], lp_err["max_abs"]))
             res["forms"][prec] = form
-            log("form %s: recall %.4f, %.0f QPS, low-precision score error max %.3g" % (
-                prec, form["recall"], form["qps"], lp_err["max_abs"]))
+    lhash = None
     if args.learned:
-        res.setdefault("forms", {})["learned"] = bench_learned(args, hf, torch, ws, forest, x, q, gt, nq)
+        res.setdefault("forms", {})["learned"], lhash = bench_learned(args, hf, torch, ws, forest, x, q, gt, nq)
     forest.free()
-    return res
+    return res, lhash
 
 
 def bench_learned(args, hf, torch, ws, forest, x, q, gt, nq):
-    """Learned sketches: the MLP hash trained by libhf on (training query, true
-    neighbour) pairs from an exact GPU brute force, then used as the forest's
-    sketches at the same (k1, k2, h); SRP is restored afterwards."""
+    """Learned sketches: the MLP hash trained by libhf on pairs the forest
+    itself generates -- for every training query its 30 best results at a
+    larger budget (positives) and, per positive, one of its C2 candidates
+    (close in SRP Hamming distance) that is not among them (hard negative) --
+    then used as the forest's sketches at the same (k1, k2, h); SRP is
+    restored afterwards.  Returns (record, the trained hash)."""
     import datagen
     import numpy as np
 
     ntr, kn = args.learned_queries, args.learned_nn
     qt = datagen.mixture_device(ntr, ws["d"], ws["n_comp"], ws["sigma"], ws["seed"], ws["unit"], draw_seed=2513)
-    log("learned hash: ground truth of %d training queries" % ntr)
-    nn = ground_truth_ip(x, qt, kn).cpu().numpy()
+    g1, g2, gh = (int(v) for v in args.learned_budget.split(","))
+    log("learned hash: forest pairs of %d training queries (k1=%d k2=%d h=%d)" % (ntr, g1, g2, gh))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    nn_l, c2_l = [], []
+    for s0 in range(0, ntr, 10000):
+        r = forest.search_debug(qt[s0:s0 + 10000], kn, g1, g2, gh)
+        nn_l.append(r["ids"].long())
+        c2_l.append(r["c2"].long())
+    nn = torch.cat(nn_l)
+    c2 = forest.pos2id().long()[torch.cat(c2_l).clamp(min=0)]
+    # per query, the C2 candidates (in Hamming order) that are not positives
+    isneg = ~(c2.unsqueeze(2) == nn.unsqueeze(1)).any(2)
+    rank = torch.cumsum(isneg.int(), 1) - 1
+    negs = torch.full((ntr, kn), -1, dtype=torch.long, device=x.device)
+    pick = isneg & (rank < kn)
+    rows_i = torch.arange(ntr, device=x.device).unsqueeze(1).expand_as(c2)
+    negs[rows_i[pick], rank[pick]] = c2[pick]
+    negs = torch.where(negs < 0, nn, negs)  # (never short at these budgets)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    nn_np = nn.cpu().numpy()
     e = forest.info["quant_exp"]
-    qi, pi = hf.hilbert_pairs(hf.quantize(qt, e), nn, 5, args.learned_batch)
+    qi, pi = hf.hilbert_pairs(hf.quantize(qt, e), nn_np, 5, args.learned_batch)
+    # the negative of pair (query, r-th positive) is the query's r-th negative
+    rk = np.repeat(np.arange(kn), len(qi) // kn)
+    ni = negs.cpu().numpy()[qi, rk]
     A = qt[torch.from_numpy(qi).to(x.device)].contiguous()
     B = x[torch.from_numpy(pi).to(x.device)].contiguous()
+    Nn = x[torch.from_numpy(ni).to(x.device)].contiguous()
     L = hf.LHash.init(ws["d"], 256, seed=7)
     torch.cuda.synchronize()
     t = time.perf_counter()
     curve = L.train(A, B, hf.train_params(epochs=args.learned_epochs, batch=args.learned_batch, lr=1e-3, tau=0.1,
-                                          slope=2.0, balance=0.05, keep_blocks=True))
+                                          slope=2.0, balance=0.05, keep_blocks=True), N=Nn)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t
-    log("learned hash trained on %d pairs in %.2f s, loss per epoch %s" % (A.shape[0], train_s, np.round(curve, 3)))
+    log("learned hash trained on %d pairs (+ as many hard negatives) in %.2f s, loss per epoch %s"
+        % (A.shape[0], train_s, np.round(curve, 3)))
+    del A, B, Nn
     t = time.perf_counter()
     forest.set_sketch("learned", L)
     torch.cuda.synchronize()
@@ -494,14 +576,16 @@ def bench_learned(args, hf, torch, ws, forest, x, q, gt, nq):
     srid, _ = forest.search(q, args.k, args.k1, args.k2, args.h)
     srec = recall(srid, gt)
     log("learned sketches: recall %.4f vs SRP %.4f at k1=%d k2=%d h=%d" % (lrec, srec, args.k1, args.k2, args.h))
-    L.free()
-    return {"recall": lrec, "recall_srp_same_budget": srec, "gain_over_srp": lrec - srec,
-            "qps": nq * args.steps / ldt, "train_pairs": int(A.shape[0]), "train_s": train_s,
-            "encode_23M_s": enc_s, "loss_per_epoch": [float(v) for v in curve],
-            "sketch_in_use": "srp" if lrec <= srec else "learned"}
+    return ({"recall": lrec, "recall_srp_same_budget": srec, "gain_over_srp": lrec - srec,
+             "qps": nq * args.steps / ldt, "train_pairs": int(len(qi)), "hard_negatives": int(len(qi)),
+             "pairs_from": "forest search k1=%d k2=%d h=%d (positives: its top %d; negatives: C2 entries not "
+                           "among them, in Hamming order)" % (g1, g2, gh, kn),
+             "pair_generation_s": gen_s, "train_s": train_s, "encode_23M_s": enc_s,
+             "loss_per_epoch": [float(v) for v in curve],
+             "sketch_in_use": "srp" if lrec <= srec else "learned"}, L)
 
 
-def bench_graph(args, hf, torch, ws, k):
+def bench_graph(args, hf, torch, ws, k, lhash):
     import datagen
 
     N = (args.n if args.workload.startswith("graph") else None) or ws["n"]
@@ -556,11 +640,42 @@ def bench_graph(args, hf, torch, ws, k):
     roof = {"bound": "hbm", "kernel": "k_band", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": rec_t[0] if rec_t else None,
             "bytes_per_launch": bytes_launch, "ms_per_launch": band_ms / band_n}
+    prefilter = None
+    if lhash is not None:
+        # the sketch stage of Alg. 2 with learned sketches against SRP and the
+        # plain form, at one setting of orders and window
+        prefilter = {}
+        po, pw, pk2 = (int(v) for v in args.prefilter.split(","))
+        for name, kw in [("learned", dict(k2=pk2, sketch="learned", lhash=lhash)),
+                         ("srp", dict(k2=pk2, sketch_seed=6)), ("plain", dict())]:
+            hf.knn_graph(x, po, pw, k, 3, **kw)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            pids, _ = hf.knn_graph(x, po, pw, k, 3, **kw)
+            torch.cuda.synchronize()
+            prefilter[name] = {"orders": po, "window": pw, "k2": kw.get("k2", 0),
+                               "recall": recall(pids[rows], gt), "s": time.perf_counter() - t}
+        log("graph sketch stage (%d orders, +-%d, k2=%d): %s" % (po, pw, pk2, {
+            n_: (round(v_["recall"], 3), round(v_["s"], 3)) for n_, v_ in prefilter.items()}))
+    table2 = None
+    if args.tables:
+        table2 = []
+        for (psec, prec_, tn, tk1, tk2) in TABLE2:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            tids, _ = hf.knn_graph(x, tn, tk1 // 2, k, 3, k2=min(tk2, 256), sketch_seed=6)
+            torch.cuda.synchronize()
+            tdt = time.perf_counter() - t
+            table2.append({"orders": tn, "window": tk1 // 2, "k2": min(tk2, 256), "recall": recall(tids[rows], gt),
+                           "s": tdt, "paper_recall": prec_, "paper_s": psec, "paper_k1": tk1, "paper_k2": tk2})
+        log("Table 2 rows on the stand-in: %s" % [(r_["orders"], r_["window"], round(r_["recall"], 3),
+                                                    round(r_["s"], 2)) for r_ in table2])
     return {"metric": "kNN-graph build s (3Mx384, k=15)", "value": dt / args.steps, "unit": "s",
             "ms_per_step": dt * 1e3 / args.steps, "recall": rec, "higher_is_better": False,
-            "config": {"workload": args.workload, "n": N, "d": d, "orders": args.orders,
+            "config": {"workload": "graph-3Mx384", "n": N, "d": d, "orders": args.orders,
                        "window": args.window, "k": k}, "roofline": roof,
-            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}}
+            "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()}, "table2": table2,
+            "prefilter": prefilter}
 
 
 def bench_configs(args, hf, torch):
@@ -629,17 +744,26 @@ def main():
     ap.add_argument("--window", type=int, default=160)
     ap.add_argument("--sweep", default=None,
                     help="extra configs: search 'k1,k2,h;...', graph 'orders,w[,k2];...'")
-    ap.add_argument("--forms", default="bf16,fp8", help="precision forms measured after the plain search")
+    ap.add_argument("--forms", default="bf16,fp8,c4",
+                    help="forms measured after the plain search: bf16, fp8 (low-precision scoring, FP32 rerank), "
+                         "c4 (sign sketches and 4-bit codes, the paper's layout)")
     ap.add_argument("--learned", type=int, default=1, help="also train and measure the learned sketch form")
-    ap.add_argument("--learned-queries", type=int, default=20000)
+    ap.add_argument("--learned-queries", type=int, default=66667,
+                    help="training queries; pairs = queries x --learned-nn (2M by default)")
+    ap.add_argument("--learned-budget", default="140,3000,1",
+                    help="'k1,k2,h' of the forest search that generates the training pairs and negatives")
     ap.add_argument("--learned-nn", type=int, default=30)
     ap.add_argument("--learned-batch", type=int, default=500)
-    ap.add_argument("--learned-epochs", type=int, default=2)
+    ap.add_argument("--learned-epochs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=1,
                     help="search workload: also time the 3M x 384 graph (--orders, --window) in the same line")
     ap.add_argument("--configs", type=int, default=1,
                     help="search workload: also run the 10K x 32 search and the 1M x 384 graph configurations")
+    ap.add_argument("--prefilter", default="128,128,256",
+                    help="graph: 'orders,window,k2' at which learned and SRP sketch stages are compared")
+    ap.add_argument("--tables", type=int, default=1,
+                    help="also re-run the paper's Table 1 (search) and Table 2 (graph) parameters once each")
     ap.add_argument("--exact", type=int, default=1,
                     help="search: also time the main budget with exact query positions (insertion ranks)")
     ap.add_argument("--c3", default="2000,1100,2,160",
@@ -688,17 +812,19 @@ def main():
     hf.lib()
     ws = datagen.WORKLOADS[args.workload]
     if args.workload.startswith("search"):
-        res = bench_search(args, hf, torch, ws)
+        res, lhash = bench_search(args, hf, torch, ws)
         torch.cuda.empty_cache()
         if args.graph:
             # the other half of the metric: the 3M x 384 k-NN graph
             log("graph-3Mx384: %d orders, window +-%d" % (args.orders, args.window))
-            res["graph"] = bench_graph(args, hf, torch, datagen.WORKLOADS["graph-3Mx384"], 15)
+            res["graph"] = bench_graph(args, hf, torch, datagen.WORKLOADS["graph-3Mx384"], 15, lhash)
             torch.cuda.empty_cache()
+        if lhash is not None:
+            lhash.free()
         if args.configs:
             res["configs"] = bench_configs(args, hf, torch)
     else:
-        res = bench_graph(args, hf, torch, ws, args.k)
+        res = bench_graph(args, hf, torch, ws, args.k, None)
     res.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "scaling": "weak",
                 "vs_baseline": None, "dtype": "f16", "data": "synthetic"})
     if not args.no_cpu_baseline:

@@ -49,10 +49,18 @@ typedef enum hf_dtype { HF_F16 = 0, HF_F32 = 1 } hf_dtype;
 typedef enum hf_precision {
   HF_PREC_FP32 = 0, /* score every expanded candidate in FP32 */
   HF_PREC_BF16 = 1, /* score in BF16 on MFMA, FP32 rerank of survivors */
-  HF_PREC_FP8 = 2   /* score in FP8 e4m3 (per-row scale) on MFMA, FP32 rerank */
+  HF_PREC_FP8 = 2,  /* score in FP8 e4m3 (per-row scale) on MFMA, FP32 rerank */
+  HF_PREC_C4 = 3    /* Section 3.1's layout: score from 4-bit codes (sign + 3-bit magnitude)
+                       with the query unquantized, FP32 accumulate */
 } hf_precision;
 
-typedef enum hf_sketch_kind { HF_SKETCH_SRP = 0, HF_SKETCH_LEARNED = 1 } hf_sketch_kind;
+/* Sketches compared by the Hamming filter:
+ *  HF_SKETCH_SRP:     512 signs of seeded random projections (default);
+ *  HF_SKETCH_LEARNED: 512 sign bits of a trained MLP (hf_lhash_*);
+ *  HF_SKETCH_SIGN:    one bit per coordinate, [x_i >= 0] (Section 3.1's d-bit
+ *                     sketches, the bit the 4-bit codes share), d <= 512,
+ *                     zero padded to 512 bits. */
+typedef enum hf_sketch_kind { HF_SKETCH_SRP = 0, HF_SKETCH_LEARNED = 1, HF_SKETCH_SIGN = 2 } hf_sketch_kind;
 
 #define HF_QUANT_AUTO INT32_MIN
 #define HF_SKETCH_BITS 512
@@ -302,17 +310,22 @@ hf_status hf_lhash_get(const hf_lhash* h, float* W1_host, float* b1_host, float*
 hf_status hf_lhash_encode(const hf_lhash* h, const void* X_dev, hf_dtype dtype, int64_t N, int32_t d,
                           uint64_t* sk_dev, void* stream);
 /* Loss (host) and FP32 gradients (device, shapes of W1, b1, W2, b2) of the
- * training objective on one batch of npairs positive pairs (A_dev[i], B_dev[i]):
- * (1/B) sum_i [log sum_j exp(S_ij/tau) - S_ii/tau] + balance * sum_b m_b^2,
- * S_ij = <c(A_i), c(B_j)> / 512, m = mean code over the 2B rows.  Synchronises. */
-hf_status hf_lhash_grad(const hf_lhash* h, const void* A_dev, const void* B_dev, hf_dtype dtype,
+ * training objective on one batch of npairs positive pairs (A_dev[i], B_dev[i])
+ * and, if N_dev is non-null, one hard negative N_dev[i] per query:
+ * (1/B) sum_i [log (sum_j exp(S_ij/tau) + exp(H_i/tau)) - S_ii/tau]
+ * + balance * sum_b m_b^2, S_ij = <c(A_i), c(B_j)> / 512, H_i = <c(A_i), c(N_i)>
+ * / 512 (the term absent without negatives), m = mean code over all rows.
+ * Synchronises. */
+hf_status hf_lhash_grad(const hf_lhash* h, const void* A_dev, const void* B_dev, const void* N_dev, hf_dtype dtype,
                         int64_t npairs, int32_t d, const hf_lhash_train_params* params, float* loss_host,
                         float* gW1_dev, float* gb1_dev, float* gW2_dev, float* gb2_dev, void* stream);
-/* AdamW training on npairs pairs (rows of A_dev and B_dev), `epochs` passes of
- * shuffled batches; loss_curve_host (nullable) receives the mean loss of each
- * epoch.  Synchronises. */
-hf_status hf_lhash_train(hf_lhash* h, const void* A_dev, const void* B_dev, hf_dtype dtype, int64_t npairs,
-                         int32_t d, const hf_lhash_train_params* params, float* loss_curve_host, void* stream);
+/* AdamW training on npairs pairs (rows of A_dev and B_dev, with the hard
+ * negatives N_dev when non-null), `epochs` passes of shuffled batches;
+ * loss_curve_host (nullable) receives the mean loss of each epoch.
+ * Synchronises. */
+hf_status hf_lhash_train(hf_lhash* h, const void* A_dev, const void* B_dev, const void* N_dev, hf_dtype dtype,
+                         int64_t npairs, int32_t d, const hf_lhash_train_params* params, float* loss_curve_host,
+                         void* stream);
 /* Replaces the forest's sketches: HF_SKETCH_SRP (from its sketch_seed) or
  * HF_SKETCH_LEARNED (lhash encodes the master-ordered rows, and queries at
  * search time).  Synchronises. */

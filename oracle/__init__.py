@@ -70,7 +70,7 @@ def lib():
             "hfo_e4m3_encode": (C.c_uint8, [C.c_float]),
             "hfo_fp8_scale": (C.c_float, [P, i32, i64, i32]),
             "hfo_mlp_forward": (None, [P, i32, i64, i32, i32, P, P, P, P, i32, P, P, P, P]),
-            "hfo_lhash_grad": (C.c_double, [P, P, i32, i64, i32, i32, P, P, P, P, C.c_double, C.c_double,
+            "hfo_lhash_grad": (C.c_double, [P, P, P, i32, i64, i32, i32, P, P, P, P, C.c_double, C.c_double,
                                             C.c_double, i32, P, P, P, P]),
             "hfo_search_lowprec": (None, [P, i32, i64, i32, P, P, P, i32, P, i64, i32, i32, i32, i32,
                                           P, P, P, P]),
@@ -371,16 +371,18 @@ def mlp_forward(x, W1, b1, W2, b2, rounded=True):
     return z1, a, z2, band
 
 
-def lhash_grad(A, B, W1, b1, W2, b2, slope, tau, lam, rounded=True):
-    """Loss and FP64 gradients of the learned-hash training objective on one batch of pairs."""
+def lhash_grad(A, B, W1, b1, W2, b2, slope, tau, lam, rounded=True, Neg=None):
+    """Loss and FP64 gradients of the learned-hash training objective on one
+    batch of pairs (A[i], B[i]), with one hard negative Neg[i] per query if given."""
     A = np.ascontiguousarray(A)
     Bm = np.ascontiguousarray(B.astype(A.dtype))
+    Ng = None if Neg is None else np.ascontiguousarray(Neg.astype(A.dtype))
     n, d = A.shape
     hid = W1.shape[0]
     f = lambda a: np.ascontiguousarray(a, np.float32)
     W1, b1, W2, b2 = f(W1), f(b1), f(W2), f(b2)
     g = [np.empty((hid, d)), np.empty(hid), np.empty((512, hid)), np.empty(512)]
-    loss = lib().hfo_lhash_grad(_p(A), _p(Bm), _dtype_code(A), n, d, hid, _p(W1), _p(b1), _p(W2), _p(b2),
+    loss = lib().hfo_lhash_grad(_p(A), _p(Bm), _p(Ng), _dtype_code(A), n, d, hid, _p(W1), _p(b1), _p(W2), _p(b2),
                                 slope, tau, lam, int(rounded), *[_p(v) for v in g])
     return float(loss), g
 

@@ -877,38 +877,50 @@ void hfo_mlp_forward(const void *x, int32_t dtype, int64_t n, int32_t d, int32_t
   }
 }
 
-double hfo_lhash_grad(const void *A, const void *Bm, int32_t dtype, int64_t B, int32_t d, int32_t hid,
-                      const float *W1, const float *b1, const float *W2, const float *b2, double slope,
+/* Loss and gradients with optional hard negatives Ng (nullable, B rows, one */
+/* per query): the softmax of query i then runs over the B in-batch          */
+/* positives and its own negative, H_i = <c(q_i), c(n_i)> / 512:             */
+/*   L = (1/B) sum_i [ log( sum_j exp(S_ij/tau) + exp(H_i/tau) ) - S_ii/tau ] */
+/*       + lambda * sum_b m_b^2, m = mean code over all rows (2B or 3B).     */
+double hfo_lhash_grad(const void *A, const void *Bm, const void *Ng, int32_t dtype, int64_t B, int32_t d,
+                      int32_t hid, const float *W1, const float *b1, const float *W2, const float *b2, double slope,
                       double tau, double lambda, int32_t rounded, double *gW1, double *gb1, double *gW2,
                       double *gb2) {
-  const int64_t R = 2 * B; /* rows: the B queries, then the B positives */
+  const int64_t R = (Ng ? 3 : 2) * B; /* rows: the B queries, the B positives, the B negatives */
   double *z1 = (double *)malloc(sizeof(double) * R * hid);
   double *a = (double *)malloc(sizeof(double) * R * hid);
   double *z2 = (double *)malloc(sizeof(double) * R * 512);
   double *c = (double *)malloc(sizeof(double) * R * 512);
   double *dc = (double *)calloc((size_t)(R * 512), sizeof(double));
-  double *S = (double *)malloc(sizeof(double) * B * B);
+  double *S = (double *)malloc(sizeof(double) * B * (B + 1));
   double *m = (double *)calloc(512, sizeof(double));
   hfo_mlp_forward(A, dtype, B, d, hid, W1, b1, W2, b2, rounded, z1, a, z2, NULL);
   hfo_mlp_forward(Bm, dtype, B, d, hid, W1, b1, W2, b2, rounded, z1 + B * hid, a + B * hid, z2 + B * 512, NULL);
+  if (Ng)
+    hfo_mlp_forward(Ng, dtype, B, d, hid, W1, b1, W2, b2, rounded, z1 + 2 * B * hid, a + 2 * B * hid,
+                    z2 + 2 * B * 512, NULL);
   for (int64_t i = 0; i < R * 512; ++i) c[i] = tanh(slope * z2[i]);
-  double loss = 0.0;
+  /* logits of row i: columns j < B the positives, column B its negative */
+  const int64_t nc = Ng ? B + 1 : B;
   for (int64_t i = 0; i < B; ++i)
-    for (int64_t j = 0; j < B; ++j) {
+    for (int64_t j = 0; j < nc; ++j) {
+      const double *o = j < B ? c + (B + j) * 512 : c + (2 * B + i) * 512;
       double acc = 0.0;
-      for (int32_t b = 0; b < 512; ++b) acc += c[i * 512 + b] * c[(B + j) * 512 + b];
-      S[i * B + j] = acc / 512.0;
+      for (int32_t b = 0; b < 512; ++b) acc += c[i * 512 + b] * o[b];
+      S[i * nc + j] = acc / 512.0;
     }
+  double loss = 0.0;
   for (int64_t i = 0; i < B; ++i) {
     double mx = -INFINITY, sum = 0.0;
-    for (int64_t j = 0; j < B; ++j) mx = fmax(mx, S[i * B + j] / tau);
-    for (int64_t j = 0; j < B; ++j) sum += exp(S[i * B + j] / tau - mx);
-    loss += (mx + log(sum) - S[i * B + i] / tau) / (double)B;
-    for (int64_t j = 0; j < B; ++j) {
-      double g = (exp(S[i * B + j] / tau - mx) / sum - (i == j ? 1.0 : 0.0)) / (tau * (double)B);
+    for (int64_t j = 0; j < nc; ++j) mx = fmax(mx, S[i * nc + j] / tau);
+    for (int64_t j = 0; j < nc; ++j) sum += exp(S[i * nc + j] / tau - mx);
+    loss += (mx + log(sum) - S[i * nc + i] / tau) / (double)B;
+    for (int64_t j = 0; j < nc; ++j) {
+      double g = (exp(S[i * nc + j] / tau - mx) / sum - (i == j ? 1.0 : 0.0)) / (tau * (double)B);
+      const int64_t orow = j < B ? B + j : 2 * B + i;
       for (int32_t b = 0; b < 512; ++b) {
-        dc[i * 512 + b] += g * c[(B + j) * 512 + b] / 512.0;
-        dc[(B + j) * 512 + b] += g * c[i * 512 + b] / 512.0;
+        dc[i * 512 + b] += g * c[orow * 512 + b] / 512.0;
+        dc[orow * 512 + b] += g * c[i * 512 + b] / 512.0;
       }
     }
   }
@@ -923,8 +935,8 @@ double hfo_lhash_grad(const void *A, const void *Bm, int32_t dtype, int64_t B, i
   memset(gb2, 0, sizeof(double) * 512);
   double *dz1 = (double *)malloc(sizeof(double) * hid);
   for (int64_t r = 0; r < R; ++r) {
-    const void *src = r < B ? A : Bm;
-    int64_t rr = r < B ? r : r - B;
+    const void *src = r < B ? A : (r < 2 * B ? Bm : Ng);
+    int64_t rr = r % B;
     for (int32_t i = 0; i < hid; ++i) dz1[i] = 0.0;
     for (int32_t j = 0; j < 512; ++j) {
       double cj = c[r * 512 + j];

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libhf.so")
 
 HF_OK = 0
 HF_F16, HF_F32 = 0, 1
-HF_PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
-HF_SKETCH_SRP, HF_SKETCH_LEARNED = 0, 1
+HF_PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "c4": 3}
+HF_SKETCH_SRP, HF_SKETCH_LEARNED, HF_SKETCH_SIGN = 0, 1, 2
 HF_POS = {"leaf": 0, "exact": 1}
 HF_QUANT_AUTO = -(2 ** 31)
 STATUS = {0: "ok", 1: "invalid argument", 2: "invalid input", 3: "out of memory", 4: "device error",
@@ -136,8 +136,8 @@ def lib():
             "hf_lhash_free": (None, [P]),
             "hf_lhash_get": (C.c_int, [P, P, P, P, P]),
             "hf_lhash_encode": (C.c_int, [P, P, C.c_int, i64, i32, P, P]),
-            "hf_lhash_grad": (C.c_int, [P, P, P, C.c_int, i64, i32, P, P, P, P, P, P, P]),
-            "hf_lhash_train": (C.c_int, [P, P, P, C.c_int, i64, i32, P, P, P]),
+            "hf_lhash_grad": (C.c_int, [P, P, P, P, C.c_int, i64, i32, P, P, P, P, P, P, P]),
+            "hf_lhash_train": (C.c_int, [P, P, P, P, C.c_int, i64, i32, P, P, P]),
             "hf_forest_set_sketch": (C.c_int, [P, C.c_int, P, P]),
             "hf_knn_graph_debug": (C.c_int, [P, C.c_int, i64, i32, P, P, P, P, P]),
             "hf_set_allocator": (C.c_int, [P]),
@@ -294,11 +294,13 @@ class Forest:
     """Hilbert forest (Algorithm 1 preprocessing) owned by libhf on the current device."""
 
     def __init__(self, x, n_trees: int, leaf_max: int = 100, seed: int = 0, sketch_seed: int = 0,
-                 quant_exp: int | None = None):
+                 quant_exp: int | None = None, sketch: str = "srp", lhash=None):
         x = _dev(x)
+        kind = {"srp": HF_SKETCH_SRP, "learned": HF_SKETCH_LEARNED, "sign": HF_SKETCH_SIGN}[sketch]
         p = ForestParams(C.sizeof(ForestParams), n_trees, leaf_max,
                          HF_QUANT_AUTO if quant_exp is None else quant_exp, seed, sketch_seed,
-                         HF_SKETCH_SRP, 0, None)
+                         kind, 0, None if lhash is None else lhash._h)
+        self._lhash = lhash
         h = C.c_void_p()
         _check(lib().hf_build_forest(_ptr(x), _dtype(x), x.shape[0], x.shape[1], C.byref(p),
                                      _stream(), C.byref(h)))
@@ -385,9 +387,9 @@ class Forest:
         return ids, sc
 
     def set_sketch(self, kind: str, lhash=None):
-        """'srp' or 'learned' (lhash must outlive the forest's use of it)."""
+        """'srp', 'learned' (lhash must outlive the forest's use of it) or 'sign'."""
         self._lhash = lhash
-        _check(lib().hf_forest_set_sketch(self._h, {"srp": HF_SKETCH_SRP, "learned": HF_SKETCH_LEARNED}[kind],
+        _check(lib().hf_forest_set_sketch(self._h, {"srp": HF_SKETCH_SRP, "learned": HF_SKETCH_LEARNED, "sign": HF_SKETCH_SIGN}[kind],
                                           None if lhash is None else lhash._h, _stream()))
 
     def add_precision(self, precision: str):
@@ -476,29 +478,34 @@ class LHash:
         _check(lib().hf_lhash_encode(self._h, _ptr(x), _dtype(x), x.shape[0], x.shape[1], _ptr(out), _stream()))
         return out
 
-    def grad(self, A, B, params):
+    def grad(self, A, B, params, N=None):
+        """Loss and gradients on pairs (A[i], B[i]), with hard negatives N[i] if given."""
         A, B = _dev(A), _dev(B)
+        N = None if N is None else _dev(N)
         t = _torch()
         g = [t.empty((self.hidden, self.d), dtype=t.float32, device=A.device),
              t.empty(self.hidden, dtype=t.float32, device=A.device),
              t.empty((512, self.hidden), dtype=t.float32, device=A.device),
              t.empty(512, dtype=t.float32, device=A.device)]
         loss = C.c_float()
-        _check(lib().hf_lhash_grad(self._h, _ptr(A), _ptr(B), _dtype(A), A.shape[0], A.shape[1], C.byref(params),
+        _check(lib().hf_lhash_grad(self._h, _ptr(A), _ptr(B), _ptr(N), _dtype(A), A.shape[0], A.shape[1],
+                                   C.byref(params),
                                    C.byref(loss), *[_ptr(v) for v in g], _stream()))
         return float(loss.value), g
 
-    def train(self, A, B, params):
+    def train(self, A, B, params, N=None):
+        """AdamW on pairs (A[i], B[i]) (hard negatives N[i] if given); loss per epoch."""
         A, B = _dev(A), _dev(B)
+        N = None if N is None else _dev(N)
         curve = np.zeros(max(1, params.epochs), np.float32)
-        _check(lib().hf_lhash_train(self._h, _ptr(A), _ptr(B), _dtype(A), A.shape[0], A.shape[1], C.byref(params),
-                                    curve.ctypes.data_as(C.c_void_p), _stream()))
+        _check(lib().hf_lhash_train(self._h, _ptr(A), _ptr(B), _ptr(N), _dtype(A), A.shape[0], A.shape[1],
+                                    C.byref(params), curve.ctypes.data_as(C.c_void_p), _stream()))
         return curve
 
 
 # ---------------------------------------------------------------- graph
 def _graph_params(n_orders, window, k, seed, k2, sketch, sketch_seed, lhash, quant_exp):
-    kind = {"srp": HF_SKETCH_SRP, "learned": HF_SKETCH_LEARNED}[sketch]
+    kind = {"srp": HF_SKETCH_SRP, "learned": HF_SKETCH_LEARNED, "sign": HF_SKETCH_SIGN}[sketch]
     return GraphParams(C.sizeof(GraphParams), n_orders, window, k, k2,
                        HF_QUANT_AUTO if quant_exp is None else quant_exp, kind, seed, sketch_seed,
                        None if lhash is None else lhash._h.value)

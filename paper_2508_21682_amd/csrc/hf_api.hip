@@ -137,7 +137,8 @@ hf_status data_exp(const void* X, hf_dtype dt, int64_t n, int32_t want, int* e, 
 void forest_release(hf_forest* f) {
   if (!f) return;
   void* ptrs[] = {f->X_pos, f->sk_pos, f->pos2id, f->tree_perm, f->nodes, f->curve_perm, f->curve_refl,
-                  f->X_bf16, f->X_fp8, f->s_fp8, f->node_off_dev, f->srp_R, f->node_aux, f->sgn_pos};
+                  f->X_bf16, f->X_fp8, f->s_fp8, f->node_off_dev, f->srp_R, f->node_aux, f->sgn_pos,
+                  f->c4_mag, f->c4_scale};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   f->magic = 0;
@@ -308,8 +309,14 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   HF_ARG(params->leaf_max >= 1, "leaf_max must be >= 1");
   HF_ARG(params->quant_exp == HF_QUANT_AUTO || (params->quant_exp >= -8 && params->quant_exp <= 24),
          "quant_exp must be HF_QUANT_AUTO or in [-8, 24]");
-  if (params->sketch != HF_SKETCH_SRP) {
-    set_error("only SRP sketches are built by hf_build_forest");
+  HF_ARG(params->sketch == HF_SKETCH_SRP || params->sketch == HF_SKETCH_LEARNED || params->sketch == HF_SKETCH_SIGN,
+         "bad sketch kind");
+  if (params->sketch == HF_SKETCH_LEARNED) {
+    HF_ARG(params->lhash != nullptr, "learned sketches need a hash");
+    HF_ARG(lhash_dim(params->lhash) == d, "the hash's input size differs from d");
+  }
+  if (params->sketch == HF_SKETCH_SIGN && d > HF_SKETCH_BITS) {
+    set_error("sign sketches need d <= %d", HF_SKETCH_BITS);
     return HF_ERR_UNSUPPORTED;
   }
   *out = nullptr;
@@ -426,8 +433,15 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   HF_TRY(srp_matrix_upload(d, params->sketch_seed, &f->srp_R, &r_bytes, s));
   {
     StageTimer tm(ST_BSKETCH, s);
-    HF_TRY(srp_sketch(f->X_pos, dtype, N, d, e, params->sketch_seed, f->sk_pos, ws, f->srp_R));
+    if (params->sketch == HF_SKETCH_LEARNED)
+      HF_TRY(lhash_encode_dev(params->lhash, f->X_pos, dtype, N, f->sk_pos, s));
+    else if (params->sketch == HF_SKETCH_SIGN)
+      HF_TRY(sign_sketch(f->X_pos, dtype, N, d, f->sk_pos, s));
+    else
+      HF_TRY(srp_sketch(f->X_pos, dtype, N, d, e, params->sketch_seed, f->sk_pos, ws, f->srp_R));
   }
+  f->sketch_kind = (int)params->sketch;
+  f->lhash = params->sketch == HF_SKETCH_LEARNED ? params->lhash : nullptr;
   HIP_TRY(hipStreamSynchronize(s));
   f->device_bytes = (int64_t)(esz * N * d + 64 * N + 4 * N + 4 * (size_t)T * N +
                               16 * (size_t)f->node_off[T] + 5 * (size_t)T * d + 8 * (size_t)(T + 1) + r_bytes +
@@ -519,7 +533,11 @@ static hf_status check_search(const hf_forest* f, const void* Q, hf_dtype dtype,
   HF_ARG(p->k1 >= 1, "k1 must be >= 1");
   HF_ARG(p->k2 >= p->k && p->k2 <= 4096, "k2 must be in [k, 4096]");
   HF_ARG(p->h <= 1024, "h must be <= 1024");
-  HF_ARG(p->precision <= HF_PREC_FP8, "bad precision %u", p->precision);
+  HF_ARG(p->precision <= HF_PREC_C4, "bad precision %u", p->precision);
+  if (p->precision == HF_PREC_C4 && !f->c4_mag) {
+    set_error("the forest has no 4-bit codes: call hf_forest_add_precision(HF_PREC_C4) first");
+    return HF_ERR_INVALID_ARG;
+  }
   if (p->precision == HF_PREC_BF16 && !f->X_bf16) {
     set_error("the forest has no BF16 copy: call hf_forest_add_precision first");
     return HF_ERR_INVALID_ARG;
@@ -528,7 +546,7 @@ static hf_status check_search(const hf_forest* f, const void* Q, hf_dtype dtype,
     set_error("the forest has no FP8 copy: call hf_forest_add_precision first");
     return HF_ERR_INVALID_ARG;
   }
-  if (p->precision != HF_PREC_FP32) {
+  if (p->precision == HF_PREC_BF16 || p->precision == HF_PREC_FP8) {
     const uint32_t S = p->survivors ? p->survivors : 4 * p->k;
     HF_ARG(S >= p->k && S <= 4096, "survivors must be in [k, 4096]");
   }
@@ -566,12 +584,14 @@ hf_status hf_search_debug(const hf_forest* f, const void* Q_dev, hf_dtype dtype,
 hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash* lhash, void* stream) {
   clear_error();
   HF_TRY(check_forest(f));
-  HF_ARG(kind == HF_SKETCH_SRP || kind == HF_SKETCH_LEARNED, "bad sketch kind");
+  HF_ARG(kind == HF_SKETCH_SRP || kind == HF_SKETCH_LEARNED || kind == HF_SKETCH_SIGN, "bad sketch kind");
   hipStream_t s = (hipStream_t)stream;
   if (kind == HF_SKETCH_LEARNED) {
     HF_ARG(lhash != nullptr, "learned sketches need a hash");
     HF_ARG(lhash_dim(lhash) == f->d, "the hash's input size differs from the forest's d");
     HF_TRY(lhash_encode_dev(lhash, f->X_pos, f->dtype, f->N, f->sk_pos, s));
+  } else if (kind == HF_SKETCH_SIGN) {
+    HF_TRY(sign_sketch(f->X_pos, f->dtype, f->N, f->d, f->sk_pos, s));
   } else {
     Workspace ws(s);
     HF_TRY(srp_sketch(f->X_pos, f->dtype, f->N, f->d, f->e, f->sketch_seed, f->sk_pos, ws, f->srp_R));
@@ -585,7 +605,8 @@ hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash
 hf_status hf_forest_add_precision(hf_forest* f, hf_precision prec, void* stream) {
   clear_error();
   HF_TRY(check_forest(f));
-  HF_ARG(prec == HF_PREC_BF16 || prec == HF_PREC_FP8, "precision must be BF16 or FP8");
+  HF_ARG(prec == HF_PREC_BF16 || prec == HF_PREC_FP8 || prec == HF_PREC_C4, "precision must be BF16, FP8 or C4");
+  if (prec == HF_PREC_C4) return make_c4(f, (hipStream_t)stream);
   return make_lowprec(f, prec, (hipStream_t)stream);
 }
 
@@ -622,7 +643,12 @@ static hf_status knn_graph(const void* X_dev, hf_dtype dtype, int64_t N, int32_t
   HF_ARG(p->k >= 1 && p->k <= 32, "k must be in [1, 32]");
   HF_ARG(p->k2 == 0 || (p->k2 >= p->k && p->k2 <= 256), "k2 must be 0 or in [k, 256]");
   HF_ARG(p->quant_exp == HF_QUANT_AUTO || (p->quant_exp >= -8 && p->quant_exp <= 24), "bad quant_exp");
-  HF_ARG(p->k2 == 0 || p->sketch == HF_SKETCH_SRP || p->sketch == HF_SKETCH_LEARNED, "bad sketch kind");
+  HF_ARG(p->k2 == 0 || p->sketch == HF_SKETCH_SRP || p->sketch == HF_SKETCH_LEARNED || p->sketch == HF_SKETCH_SIGN,
+         "bad sketch kind");
+  if (p->k2 > 0 && p->sketch == HF_SKETCH_SIGN && d > HF_SKETCH_BITS) {
+    set_error("sign sketches need d <= %d", HF_SKETCH_BITS);
+    return HF_ERR_UNSUPPORTED;
+  }
   HF_ARG(((uintptr_t)X_dev & 15) == 0, "X_dev must be 16-byte aligned");
   if (dtype != HF_F16 || d % 8 != 0) {
     set_error("the graph kernels take fp16 rows with d a multiple of 8");

@@ -578,6 +578,8 @@ static hf_status graph_prefilter(const void* X, int64_t N, int d, const hf_graph
   HF_TRY(ws.alloc(&sk, (size_t)N * 8));
   if (p.sketch == HF_SKETCH_LEARNED) {
     HF_TRY(lhash_encode_dev(p.lhash, X, HF_F16, N, sk, s));
+  } else if (p.sketch == HF_SKETCH_SIGN) {
+    HF_TRY(sign_sketch(X, HF_F16, N, d, sk, s));
   } else {
     HF_TRY(srp_sketch(X, HF_F16, N, d, e, p.sketch_seed, sk, ws));
   }

@@ -304,6 +304,11 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
                         int32_t* ids, float* scores, uint32_t* win_out, uint32_t* c2_out,
                         int32_t* c2n_out, int32_t* en_out, uint32_t* surv_pos, float* surv_score,
                         hipStream_t s, Workspace* ws = nullptr);
+// hf_c4.hip: the paper's compressed layout (sign sketches, 4-bit codes)
+hf_status sign_sketch(const void* X, hf_dtype dt, int64_t N, int d, uint64_t* out, hipStream_t s);
+hf_status make_c4(hf_forest* f, hipStream_t s);
+hf_status rerank_c4_launch(const hf_forest* f, const void* Qb, int64_t nb, const uint32_t* c2b, const int32_t* c2nb,
+                           int k2, int h, int k, int32_t* idsb, float* scb, int32_t* enb, hipStream_t s);
 // hf_bfilter.hip: the Hamming filter by master-position bucket.  Writes C2
 // and its count for the queries it completes and flag[q] = 0 for them,
 // flag[q] = 1 for the queries the entry-by-entry filter must redo.
@@ -340,6 +345,8 @@ struct hf_forest {
   uint32_t* node_aux;    // per node {m, b} (internal) or {lo, NONE} (leaf), same offsets
   uint32_t* sgn_pos;     // N x sgn_words top bits of the codes (coordinate signs), master order
   int sgn_words;         // 32-bit words per row of sgn_pos (0: d too large, no exact rank)
+  uint32_t* c4_mag;      // N x sgn_words x 3 magnitude bit planes of the 4-bit codes, or null
+  float* c4_scale;       // N scales of the 4-bit codes (max |x| / 8)
   std::vector<int64_t> node_off;  // T+1 offsets (in nodes)
   int64_t* node_off_dev; // the same offsets on the device
   uint64_t* srp_R;       // SRP projection matrix of (d, sketch_seed) on the device

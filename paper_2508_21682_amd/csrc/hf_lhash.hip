@@ -199,21 +199,52 @@ __global__ void k_tanh(const float* __restrict__ z, int64_t n, float slope, floa
 }
 
 // Row-wise softmax gradient of the InfoNCE loss: G = (softmax(S/tau) - I) / (tau*B);
-// per-row loss terms to rl.  One wavefront per row.
-__global__ void k_infonce(const float* __restrict__ S, int B, float tau, float* __restrict__ G,
-                          float* __restrict__ rl) {
+// per-row loss terms to rl.  With hard negatives (Hn non-null) row i has one
+// more logit Hn[i], whose gradient goes to Gn[i].  One wavefront per row.
+__global__ void k_infonce(const float* __restrict__ S, const float* __restrict__ Hn, int B, float tau,
+                          float* __restrict__ G, float* __restrict__ Gn, float* __restrict__ rl) {
   const int i = blockIdx.x * 4 + threadIdx.x / 64;
   if (i >= B) return;
   const float* s = S + (int64_t)i * B;
-  float mx = -INFINITY;
+  float mx = Hn ? Hn[i] / tau : -INFINITY;
   for (int j = __lane_id(); j < B; j += 64) mx = fmaxf(mx, s[j] / tau);
   for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
   float sum = 0.f;
   for (int j = __lane_id(); j < B; j += 64) sum += expf(s[j] / tau - mx);
   for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+  if (Hn) sum += expf(Hn[i] / tau - mx);
   for (int j = __lane_id(); j < B; j += 64)
     G[(int64_t)i * B + j] = (expf(s[j] / tau - mx) / sum - (i == j ? 1.f : 0.f)) / (tau * (float)B);
-  if (__lane_id() == 0) rl[i] = (mx + logf(sum) - s[i] / tau) / (float)B;
+  if (__lane_id() == 0) {
+    if (Hn) Gn[i] = expf(Hn[i] / tau - mx) / sum / (tau * (float)B);
+    rl[i] = (mx + logf(sum) - s[i] / tau) / (float)B;
+  }
+}
+
+// Hn[i] = <Cq_i, Cn_i> / 512 (a wavefront per row).
+__global__ void k_rowdot(const float* __restrict__ Cq, const float* __restrict__ Cn, int B,
+                         float* __restrict__ Hn) {
+  const int i = blockIdx.x * 4 + threadIdx.x / 64;
+  if (i >= B) return;
+  float a = 0.f;
+  for (int b = __lane_id(); b < 512; b += 64) a += Cq[(int64_t)i * 512 + b] * Cn[(int64_t)i * 512 + b];
+  for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+  if (__lane_id() == 0) Hn[i] = a / 512.f;
+}
+
+// The negative logit's part of the code gradients: dCq_i += Gn_i Cn_i / 512,
+// dCn_i = Gn_i Cq_i / 512.
+__global__ void k_neg_grad(const float* __restrict__ Cq, const float* __restrict__ Cn, const float* __restrict__ Gn,
+                           int B, float* __restrict__ dCq, float* __restrict__ dCn) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < (int64_t)B * 512; t += (int64_t)gridDim.x * 256) {
+    const float g = Gn[t / 512] / 512.f;
+    dCq[t] += g * Cn[t];
+    dCn[t] = g * Cq[t];
+  }
+}
+
+__global__ void k_zero_f32(float* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.f;
 }
 
 // Column means of C (R x 512) and the balance part of the loss.
@@ -341,12 +372,13 @@ hf_status refresh_bf16(hf_lhash* L, hipStream_t s) {
   return HF_OK;
 }
 
-// Loss and gradients (device) of one batch of B pairs: rows A[0..B) and P[0..B).
-hf_status lhash_grad(const hf_lhash* L, const void* A, const void* P, hf_dtype dt, int B,
+// Loss (added to *loss_dev) and gradients (device) of one batch of B pairs:
+// rows A[0..B) and P[0..B), and hard negatives Ng[0..B) when Ng is non-null.
+hf_status lhash_grad(const hf_lhash* L, const void* A, const void* P, const void* Ng, hf_dtype dt, int B,
                      const hf_lhash_train_params& tp, float* loss_dev, float* gW1, float* gb1, float* gW2,
                      float* gb2, Workspace& ws) {
   hipStream_t s = ws.stream;
-  const int R = 2 * B, hid = L->hid, d = L->d;
+  const int R = (Ng ? 3 : 2) * B, hid = L->hid, d = L->d;
   const size_t esz = dt == HF_F16 ? 2 : 4;
   uint16_t* H;
   float *Z, *Cc, *S, *G, *dC, *m, *rl, *dZ, *Hf, *dH, *Xf;
@@ -364,19 +396,30 @@ hf_status lhash_grad(const hf_lhash* L, const void* A, const void* P, hf_dtype d
   HF_TRY(ws.alloc(&Xf, (size_t)R * d));
   HF_TRY(lhash_forward(L, A, dt, B, H, Z, nullptr, s));
   HF_TRY(lhash_forward(L, P, dt, B, H + (size_t)B * hid, Z + (size_t)B * 512, nullptr, s));
+  if (Ng) HF_TRY(lhash_forward(L, Ng, dt, B, H + (size_t)2 * B * hid, Z + (size_t)2 * B * 512, nullptr, s));
   k_tanh<<<grid_for((int64_t)R * 512), 256, 0, s>>>(Z, (int64_t)R * 512, tp.slope, Cc);
   HF_LAUNCH_CHECK();
   const float* Cq = Cc;
   const float* Cp = Cc + (size_t)B * 512;
   // S = Cq Cp^T / 512
   HF_TRY(sgemm(s, B, B, 512, 1.f / 512.f, Cq, 512, 1, Cp, 1, 512, 0.f, S, B));
-  k_infonce<<<(unsigned)ceil_div(B, 4), 256, 0, s>>>(S, B, tp.tau, G, rl);
+  float *Hn = nullptr, *Gn = nullptr;
+  if (Ng) {
+    HF_TRY(ws.alloc(&Hn, (size_t)B));
+    HF_TRY(ws.alloc(&Gn, (size_t)B));
+    k_rowdot<<<(unsigned)ceil_div(B, 4), 256, 0, s>>>(Cq, Cc + (size_t)2 * B * 512, B, Hn);
+  }
+  k_infonce<<<(unsigned)ceil_div(B, 4), 256, 0, s>>>(S, Hn, B, tp.tau, G, Gn, rl);
   HF_LAUNCH_CHECK();
   // dCq = G Cp / 512 ; dCp = G^T Cq / 512
   HF_TRY(sgemm(s, B, 512, B, 1.f / 512.f, G, B, 1, Cp, 512, 1, 0.f, dC, 512));
   HF_TRY(sgemm(s, B, 512, B, 1.f / 512.f, G, 1, B, Cq, 512, 1, 0.f, dC + (size_t)B * 512, 512));
+  if (Ng) {
+    k_neg_grad<<<grid_for((int64_t)B * 512), 256, 0, s>>>(Cq, Cc + (size_t)2 * B * 512, Gn, B, dC,
+                                                           dC + (size_t)2 * B * 512);
+    HF_LAUNCH_CHECK();
+  }
   k_colmean<<<2, 256, 0, s>>>(Cc, R, m);
-  HIP_TRY(hipMemsetAsync(loss_dev, 0, 4, s));
   k_loss<<<1, 256, 0, s>>>(rl, B, m, tp.balance, loss_dev);
   k_dz2<<<grid_for((int64_t)R * 512), 256, 0, s>>>(dC, Cc, m, R, tp.balance, tp.slope, dZ);
   k_bf16_rows_to_f32<<<grid_for((int64_t)R * hid), 256, 0, s>>>(H, (int64_t)R * hid, Hf);
@@ -392,12 +435,14 @@ hf_status lhash_grad(const hf_lhash* L, const void* A, const void* P, hf_dtype d
   HF_TRY(sgemm(s, R, hid, 512, 1.f, dZ, 512, 1, W2f, hid, 1, 0.f, dH, hid));
   k_relu_grad<<<grid_for((int64_t)R * hid), 256, 0, s>>>(dH, H, (int64_t)R * hid, dH);
   // dW1 = dZ1^T bf16(X) ; db1 = colsum(dZ1)
-  if (dt == HF_F16) {
-    k_rows_to_bf16f<__half><<<grid_for((int64_t)B * d), 256, 0, s>>>((const __half*)A, (int64_t)B * d, Xf);
-    k_rows_to_bf16f<__half><<<grid_for((int64_t)B * d), 256, 0, s>>>((const __half*)P, (int64_t)B * d, Xf + (size_t)B * d);
-  } else {
-    k_rows_to_bf16f<float><<<grid_for((int64_t)B * d), 256, 0, s>>>((const float*)A, (int64_t)B * d, Xf);
-    k_rows_to_bf16f<float><<<grid_for((int64_t)B * d), 256, 0, s>>>((const float*)P, (int64_t)B * d, Xf + (size_t)B * d);
+  const void* srcs[3] = {A, P, Ng};
+  for (int part = 0; part < R / B; ++part) {
+    if (dt == HF_F16)
+      k_rows_to_bf16f<__half><<<grid_for((int64_t)B * d), 256, 0, s>>>((const __half*)srcs[part], (int64_t)B * d,
+                                                                        Xf + (size_t)part * B * d);
+    else
+      k_rows_to_bf16f<float><<<grid_for((int64_t)B * d), 256, 0, s>>>((const float*)srcs[part], (int64_t)B * d,
+                                                                       Xf + (size_t)part * B * d);
   }
   HF_LAUNCH_CHECK();
   HF_TRY(sgemm(s, hid, d, R, 1.f, dH, 1, hid, Xf, d, 1, 0.f, gW1, d));
@@ -524,8 +569,8 @@ static hf_status check_tp(const hf_lhash_train_params* tp) {
   return HF_OK;
 }
 
-hf_status hf_lhash_grad(const hf_lhash* L, const void* A_dev, const void* B_dev, hf_dtype dtype, int64_t npairs,
-                        int32_t d, const hf_lhash_train_params* tp, float* loss_host, float* gW1_dev,
+hf_status hf_lhash_grad(const hf_lhash* L, const void* A_dev, const void* B_dev, const void* N_dev, hf_dtype dtype,
+                        int64_t npairs, int32_t d, const hf_lhash_train_params* tp, float* loss_host, float* gW1_dev,
                         float* gb1_dev, float* gW2_dev, float* gb2_dev, void* stream) {
   clear_error();
   HF_TRY(check_lhash(L));
@@ -537,14 +582,16 @@ hf_status hf_lhash_grad(const hf_lhash* L, const void* A_dev, const void* B_dev,
   Workspace ws(s);
   float* loss;
   HF_TRY(ws.alloc(&loss, 1));
-  HF_TRY(lhash_grad(L, A_dev, B_dev, dtype, (int)npairs, *tp, loss, gW1_dev, gb1_dev, gW2_dev, gb2_dev, ws));
+  k_zero_f32<<<1, 64, 0, s>>>(loss, 1);
+  HF_TRY(lhash_grad(L, A_dev, B_dev, N_dev, dtype, (int)npairs, *tp, loss, gW1_dev, gb1_dev, gW2_dev, gb2_dev, ws));
   HIP_TRY(hipMemcpyAsync(loss_host, loss, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return HF_OK;
 }
 
-hf_status hf_lhash_train(hf_lhash* L, const void* A_dev, const void* B_dev, hf_dtype dtype, int64_t npairs,
-                         int32_t d, const hf_lhash_train_params* tp, float* loss_curve_host, void* stream) {
+hf_status hf_lhash_train(hf_lhash* L, const void* A_dev, const void* B_dev, const void* N_dev, hf_dtype dtype,
+                         int64_t npairs, int32_t d, const hf_lhash_train_params* tp, float* loss_curve_host,
+                         void* stream) {
   clear_error();
   HF_TRY(check_lhash(L));
   HF_TRY(check_tp(tp));
@@ -559,10 +606,11 @@ hf_status hf_lhash_train(hf_lhash* L, const void* A_dev, const void* B_dev, hf_d
   float *g[4], *loss;
   for (int i = 0; i < 4; ++i) HF_TRY(ws.alloc(&g[i], (size_t)n[i]));
   HF_TRY(ws.alloc(&loss, 1));
-  void *Ab, *Bb;
+  void *Ab, *Bb, *Nb = nullptr;
   uint32_t* idx;
   HF_TRY(ws.alloc((char**)&Ab, (size_t)B * d * esz));
   HF_TRY(ws.alloc((char**)&Bb, (size_t)B * d * esz));
+  if (N_dev) HF_TRY(ws.alloc((char**)&Nb, (size_t)B * d * esz));
   HF_TRY(ws.alloc(&idx, (size_t)npairs));
   std::vector<uint32_t> perm((size_t)npairs);
   uint64_t st = tp->seed;
@@ -581,19 +629,23 @@ hf_status hf_lhash_train(hf_lhash* L, const void* A_dev, const void* B_dev, hf_d
         std::swap(perm[(size_t)i], perm[(size_t)(splitmix64_next(&st) % (uint64_t)(i + 1))]);
     }
     HIP_TRY(hipMemcpyAsync(idx, perm.data(), 4 * (size_t)npairs, hipMemcpyHostToDevice, s));
-    if (loss_curve_host) loss_curve_host[ep] = 0.f;
+    k_zero_f32<<<1, 64, 0, s>>>(loss, 1);  // the epoch's loss, summed on the device
     for (int64_t it = 0; it < steps_per_epoch; ++it) {
       const uint32_t* bi = idx + it * B;
       if (dtype == HF_F16) {
         k_gather<__half><<<grid_for((int64_t)B * d), 256, 0, s>>>((const __half*)A_dev, d, bi, B, (__half*)Ab);
         k_gather<__half><<<grid_for((int64_t)B * d), 256, 0, s>>>((const __half*)B_dev, d, bi, B, (__half*)Bb);
+        if (N_dev)
+          k_gather<__half><<<grid_for((int64_t)B * d), 256, 0, s>>>((const __half*)N_dev, d, bi, B, (__half*)Nb);
       } else {
         k_gather<float><<<grid_for((int64_t)B * d), 256, 0, s>>>((const float*)A_dev, d, bi, B, (float*)Ab);
         k_gather<float><<<grid_for((int64_t)B * d), 256, 0, s>>>((const float*)B_dev, d, bi, B, (float*)Bb);
+        if (N_dev)
+          k_gather<float><<<grid_for((int64_t)B * d), 256, 0, s>>>((const float*)N_dev, d, bi, B, (float*)Nb);
       }
       HF_LAUNCH_CHECK();
       Workspace wstep(s);
-      HF_TRY(lhash_grad(L, Ab, Bb, dtype, B, *tp, loss, g[0], g[1], g[2], g[3], wstep));
+      HF_TRY(lhash_grad(L, Ab, Bb, Nb, dtype, B, *tp, loss, g[0], g[1], g[2], g[3], wstep));
       L->step += 1;
       const float c1 = 1.f - powf(tp->beta1, (float)L->step), c2 = 1.f - powf(tp->beta2, (float)L->step);
       float* w[4] = {L->W1, L->b1, L->W2, L->b2};
@@ -604,12 +656,12 @@ hf_status hf_lhash_train(hf_lhash* L, const void* A_dev, const void* B_dev, hf_d
       }
       HF_LAUNCH_CHECK();
       HF_TRY(refresh_bf16(L, s));
-      if (loss_curve_host) {
-        float h = 0.f;
-        HIP_TRY(hipMemcpyAsync(&h, loss, 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        loss_curve_host[ep] += h / (float)steps_per_epoch;
-      }
+    }
+    if (loss_curve_host) {
+      float h = 0.f;
+      HIP_TRY(hipMemcpyAsync(&h, loss, 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      loss_curve_host[ep] = h / (float)steps_per_epoch;
     }
   }
   HIP_TRY(hipStreamSynchronize(s));

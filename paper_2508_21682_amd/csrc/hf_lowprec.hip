@@ -1,14 +1,14 @@
 // Precision form of the final selection: the expansion set E of a query is
-// scored in BF16 or FP8 (OCP e4m3 with one scale per vector) on MFMA with FP32
+// scored in BF16 or FP8 (OCP e4m3 with one scale per vector) with FP32
 // accumulation, the best S "survivors" are rescored in FP32 from the stored
 // rows, and the top-k of those is the result.  FP64 appears only in the audit
 // kernel, which recomputes given (query, id) scores exactly.
 //
-// MFMA use: a wavefront scores 16 rows of E at a time; the rows are the A
-// operand (one row per lane mod 16) and the query, replicated over the 16
-// columns, is the B operand, so every column of the 16x16 result holds the 16
-// scores.  The path is bound by HBM (one read of each row), not by the matrix
-// cores.
+// Scoring E is one query against |E| distinct rows: a matrix-vector product,
+// bound by reading the rows (BF16: 2d bytes, FP8: d + 4 bytes a row), so it
+// runs on the vector ALUs: a 16-lane group per row, 16-byte loads, several
+// rows in flight per group, exact products of the rounded values summed in
+// FP32.
 #include <math.h>
 
 #include "hf_internal.h"
@@ -17,9 +17,6 @@
 namespace hf {
 namespace {
 
-typedef float float4v __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef int int8v __attribute__((ext_vector_type(8)));
 
 // Round-to-nearest-even float -> bfloat16 bits (finite input).
 __device__ __forceinline__ uint32_t bf16_bits(float f) {
@@ -76,10 +73,23 @@ __global__ void k_make_fp8(const T* __restrict__ X, int64_t N, int d, uint8_t* _
   if (__lane_id() == 0) scale[r] = s;
 }
 
-constexpr int LP_T = 512;
+constexpr int LP_T = 256;
 
-// PREC 1 = BF16 (KS = d/32 MFMA steps of K = 32), 2 = FP8 (KS = d/128 steps of K = 128).
-template <class T, int PREC, int KS>
+constexpr int LP_ROWS = 4;
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float bf16_val(uint32_t b) { return __uint_as_float(b << 16); }
+
+// Value of an OCP e4m3 code (bias 7, subnormals 2^-9 m; 0x7F never occurs).
+__device__ __forceinline__ float e4m3_val(uint32_t c) {
+  const uint32_t E = (c >> 3) & 15u, m = c & 7u;
+  const float v = E ? __uint_as_float(((E + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+  return (c & 0x80u) ? -v : v;
+}
+
+// PREC 1 = BF16, 2 = FP8; MCH 16-byte chunks of a low-precision row per lane
+// of a 16-lane group, RCH of a stored row (rescoring).
+template <class T, int PREC, int MCH, int RCH>
 __global__ __launch_bounds__(LP_T) void k_rerank_lp(
     const T* __restrict__ Xp, const void* __restrict__ Xlp, const float* __restrict__ s8,
     int64_t N, int d, const T* __restrict__ Q, const uint32_t* __restrict__ c2,
@@ -94,6 +104,7 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
   uint32_t* ekey = off + k2p + 4;                             // emax
   uint64_t* sel = (uint64_t*)(((uintptr_t)(ekey + emax) + 7) & ~(uintptr_t)7);  // sp
   uint64_t* fin = sel + sp;                                   // sp
+  float* sqr = (float*)(((uintptr_t)(fin + sp) + 15) & ~(uintptr_t)15);  // d: the rounded query
   __shared__ uint32_t hist[256];
   __shared__ uint32_t scan_tmp[LP_T / 64 + 1];
   __shared__ uint32_t s_E, s_prefix, s_lt, s_want, s_nsel;
@@ -109,7 +120,7 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
   expansion_intervals<LP_T>(sc, n2, h, N, st, off, scan_tmp, &s_E);
   const uint32_t E = s_E;
 
-  // the query in the MFMA B layout, per lane
+  // the query rounded to the format (FP8: codes of q / qscale), as floats
   float qscale = 1.f;
   if constexpr (PREC == 2) {
     float m = 0.f;
@@ -122,87 +133,67 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
     for (int i = 0; i < LP_T / 64; ++i) m = fmaxf(m, s_qmax[i]);
     qscale = m > 0.f ? __fdiv_rn(m, 448.0f) : 1.0f;
   }
-  uint32_t qb[KS][PREC == 1 ? 4 : 8];
+  for (int i = threadIdx.x; i < d; i += LP_T)
+    sqr[i] = PREC == 1 ? bf16_val(bf16_bits(sq[i])) : e4m3_val(e4m3_bits(__fdiv_rn(sq[i], qscale)));
+  __syncthreads();
+  // low-precision scores of E: a 16-lane group per row, 16-byte chunks of
+  // the row (8 BF16 or 16 FP8 values), LP_ROWS rows in flight per group;
+  // products of rounded values are exact in FP32, sums accumulate in FP32
+  {
+    const int grp = threadIdx.x / 16, gl = threadIdx.x % 16;
+    constexpr int NG = LP_T / 16;
+    constexpr int EPC = PREC == 1 ? 8 : 16;  // values per 16-byte chunk
+    const int nch = d / EPC;
+    for (uint32_t e0 = (uint32_t)grp * LP_ROWS; e0 < E; e0 += NG * LP_ROWS) {
+      uint4 raw[LP_ROWS][MCH];
+      float rs[LP_ROWS];
 #pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    if constexpr (PREC == 1) {
+      for (int u = 0; u < LP_ROWS; ++u) {
+        const uint32_t e = e0 + u;
+        const uint32_t p = e < E ? epos(st, off, n2, e) : 0u;
+        const unsigned char* row = (const unsigned char*)Xlp + (int64_t)p * d * (PREC == 1 ? 2 : 1);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k0 = 32 * s + 8 * g + 2 * v;
-        const uint32_t lo = k0 < d ? bf16_bits(sq[k0]) : 0u;
-        const uint32_t hi = k0 + 1 < d ? bf16_bits(sq[k0 + 1]) : 0u;
-        qb[s][v] = lo | (hi << 16);
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        uint32_t w = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int kk = 128 * s + 32 * g + 4 * v + b;
-          const uint32_t c = kk < d ? e4m3_bits(__fdiv_rn(sq[kk], qscale)) : 0u;
-          w |= c << (8 * b);
+        for (int m = 0; m < MCH; ++m) {
+          const int c = gl + 16 * m;
+          raw[u][m] = *(const uint4*)(row + 16 * (c < nch ? c : 0));
         }
-        qb[s][v] = w;
-      }
-    }
-  }
-  // low-precision scores of E: 16 rows per wavefront step
-  for (uint32_t e0 = (uint32_t)wv * 16; e0 < E; e0 += (LP_T / 64) * 16) {
-    const uint32_t e = e0 + (l % 16);
-    const bool ok = e < E;
-    const uint32_t p = ok ? epos(st, off, n2, e) : 0u;
-    // FP8: the row's scale, fetched with its codes (lane l holds row l % 16)
-    float rs = 1.f;
-    if constexpr (PREC == 2) rs = s8[p];  // (position 0 when past E: never used)
-    float4v acc = {0.f, 0.f, 0.f, 0.f};
-    // Row loads are unconditional (rows past E read position 0 and their
-    // scores are not stored; chunks past d are zeroed after the load): a
-    // load some lanes skip would be waited for chunk by chunk.
-    if constexpr (PREC == 1) {
-      const uint16_t* row = (const uint16_t*)Xlp + (int64_t)p * d;
-      uint4 a[KS];
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int k0 = 32 * s + 8 * g;
-        a[s] = *(const uint4*)(row + (k0 < d ? k0 : 0));
+        rs[u] = PREC == 2 ? s8[p] : 1.f;
       }
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        if (32 * s + 8 * g >= d) a[s] = make_uint4(0, 0, 0, 0);
-        uint4 b = make_uint4(qb[s][0], qb[s][1], qb[s][2], qb[s][3]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[s]),
-                                                      __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
-      }
-    } else {
-      const uint8_t* row = (const uint8_t*)Xlp + (int64_t)p * d;
+      for (int u = 0; u < LP_ROWS; ++u) {
+        float a = 0.f;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const int k0 = 128 * s + 32 * g;
-        uint4 a0 = *(const uint4*)(row + (k0 < d ? k0 : 0));
-        uint4 a1 = *(const uint4*)(row + (k0 + 16 < d ? k0 + 16 : 0));
-        if (k0 >= d) a0 = make_uint4(0, 0, 0, 0);
-        if (k0 + 16 >= d) a1 = make_uint4(0, 0, 0, 0);
-        int8v A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
-        int8v B = {(int)qb[s][0], (int)qb[s][1], (int)qb[s][2], (int)qb[s][3],
-                   (int)qb[s][4], (int)qb[s][5], (int)qb[s][6], (int)qb[s][7]};
-        // format 0 = FP8 e4m3 for both operands; block scales 2^0 (E8M0 127)
-        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(A, B, acc, 0, 0, 0, 127, 0, 127);
-      }
-    }
-    // lane l holds rows 4*(l/16)+r of the block (every column is the same)
-    float rsc[4];
+        for (int m = 0; m < MCH; ++m) {
+          const int c = gl + 16 * m;
+          if (c < nch) {
+            const float4* q4 = (const float4*)(sqr + c * EPC);  // 16-byte LDS reads
+            const uint32_t w[4] = {raw[u][m].x, raw[u][m].y, raw[u][m].z, raw[u][m].w};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) rsc[r] = __shfl(rs, 4 * g + r);
-    if (l % 16 == 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const uint32_t er = e0 + 4 * g + r;
-        if (er < E) {
-          float v = acc[r];
-          if constexpr (PREC == 2) v = v * (rsc[r] * qscale);
-          ekey[er] = ~float_to_ordered(v);
+            for (int j = 0; j < 4; ++j) {
+              if constexpr (PREC == 1) {
+                const float4 qa = q4[j >> 1];
+                const float q0 = (j & 1) ? qa.z : qa.x, q1 = (j & 1) ? qa.w : qa.y;
+                a = fmaf(bf16_val(w[j] & 0xFFFFu), q0, a);
+                a = fmaf(bf16_val(w[j] >> 16), q1, a);
+              } else {
+                // gfx950 converts OCP e4m3 pairs to FP32 in one instruction
+                const float4 qa = q4[j];
+                const float2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[j], false);
+                const float2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[j], true);
+                a = fmaf(lo.x, qa.x, a);
+                a = fmaf(lo.y, qa.y, a);
+                a = fmaf(hi.x, qa.z, a);
+                a = fmaf(hi.y, qa.w, a);
+              }
+            }
+          }
         }
+        a += __shfl_xor(a, 8);
+        a += __shfl_xor(a, 4);
+        a += __shfl_xor(a, 2);
+        a += __shfl_xor(a, 1);
+        if (PREC == 2) a = a * (rs[u] * qscale);
+        if (gl == 0 && e0 + u < E) ekey[e0 + u] = ~float_to_ordered(a);
       }
     }
   }
@@ -220,14 +211,41 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
       surv_score[q * S + i] = v ? ordered_to_float(~(uint32_t)(sel[i] >> 32)) : -INFINITY;
     }
   }
-  // FP32 rescoring of the survivors from the stored rows
+  // FP32 rescoring of the survivors from the stored rows (16-byte chunks)
   {
     const int grp = threadIdx.x / 16, gl = threadIdx.x % 16;
+    constexpr int EPC = 16 / sizeof(T);
+    const int nch = d / EPC;
     for (int i = grp; i < (int)ns; i += LP_T / 16) {
       const uint32_t p = epos(st, off, n2, (uint32_t)sel[i]);
-      const T* row = Xp + (int64_t)p * d;
+      const unsigned char* row = (const unsigned char*)(Xp + (int64_t)p * d);
+      uint4 raw[RCH];
+#pragma unroll
+      for (int m = 0; m < RCH; ++m) {
+        const int c = gl + 16 * m;
+        raw[m] = *(const uint4*)(row + 16 * (c < nch ? c : 0));
+      }
       float a = 0.f;
-      for (int c = gl; c < d; c += 16) a = fmaf(ldf(row, c), sq[c], a);
+#pragma unroll
+      for (int m = 0; m < RCH; ++m) {
+        const int c = gl + 16 * m;
+        if (c < nch) {
+          const float* qq = sq + c * EPC;
+          if constexpr (sizeof(T) == 2) {
+            const __half2* hv = (const __half2*)&raw[m];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const float2 f2 = __half22float2(hv[j]);
+              a = fmaf(f2.x, qq[2 * j], a);
+              a = fmaf(f2.y, qq[2 * j + 1], a);
+            }
+          } else {
+            const float* fv = (const float*)&raw[m];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a = fmaf(fv[j], qq[j], a);
+          }
+        }
+      }
       a += __shfl_xor(a, 8);
       a += __shfl_xor(a, 4);
       a += __shfl_xor(a, 2);
@@ -304,38 +322,37 @@ hf_status rerank_lp_launch(const hf_forest* f, hf_precision prec, const void* Qb
                            int32_t* idsb, float* scb, uint32_t* surv_pos, float* surv_score,
                            int32_t* enb, hipStream_t s) {
   const int d = f->d;
-  const int ks = prec == HF_PREC_BF16 ? d / 32 : (d + 127) / 128;
   const int k2p = [&] { int v = 1; while (v < k2) v <<= 1; return v; }();
   const int sp = [&] { int v = 1; while (v < S) v <<= 1; return v; }();
   const int64_t emax = std::min<int64_t>((int64_t)k2 * (2 * h + 1), f->N);
   const size_t smem = sizeof(float) * (((size_t)d + 3) & ~(size_t)3) + 4 * (3 * (size_t)k2p + 4) +
-                      4 * (size_t)emax + 8 + 16 * (size_t)sp;
+                      4 * (size_t)emax + 8 + 16 * (size_t)sp + 4 * (size_t)d + 16;
   if (smem > 160 * 1024) {
     set_error("low-precision rerank needs %zu bytes of LDS (k2*(2h+1) or survivors too large)", smem);
     return HF_ERR_UNSUPPORTED;
   }
   const void* kern = nullptr;
-#define HF_LP(TY, P, K) \
-  if (ks == K) kern = (const void*)k_rerank_lp<TY, P, K>;
+  // chunks per lane: low-precision rows (BF16: d/8 chunks, FP8: d/16) and
+  // stored rows (fp16: d/8, fp32: d/4), over 16 lanes
+#define HF_LP(DV, TY, P, M, R) \
+  if (d == DV && prec == (P == 1 ? HF_PREC_BF16 : HF_PREC_FP8)) kern = (const void*)k_rerank_lp<TY, P, M, R>;
   if (f->dtype == HF_F16) {
-    if (prec == HF_PREC_BF16) {
-      HF_LP(__half, 1, 4) HF_LP(__half, 1, 8) HF_LP(__half, 1, 12) HF_LP(__half, 1, 16) HF_LP(__half, 1, 24) HF_LP(__half, 1, 32)
-    } else {
-      HF_LP(__half, 2, 1) HF_LP(__half, 2, 2) HF_LP(__half, 2, 3) HF_LP(__half, 2, 4) HF_LP(__half, 2, 6) HF_LP(__half, 2, 8)
-    }
+    HF_LP(128, __half, 1, 1, 1) HF_LP(256, __half, 1, 2, 2) HF_LP(384, __half, 1, 3, 3) HF_LP(512, __half, 1, 4, 4)
+    HF_LP(768, __half, 1, 6, 6) HF_LP(1024, __half, 1, 8, 8)
+    HF_LP(128, __half, 2, 1, 1) HF_LP(256, __half, 2, 1, 2) HF_LP(384, __half, 2, 2, 3) HF_LP(512, __half, 2, 2, 4)
+    HF_LP(768, __half, 2, 3, 6) HF_LP(1024, __half, 2, 4, 8)
   } else {
-    if (prec == HF_PREC_BF16) {
-      HF_LP(float, 1, 4) HF_LP(float, 1, 8) HF_LP(float, 1, 12) HF_LP(float, 1, 16) HF_LP(float, 1, 24) HF_LP(float, 1, 32)
-    } else {
-      HF_LP(float, 2, 1) HF_LP(float, 2, 2) HF_LP(float, 2, 3) HF_LP(float, 2, 4) HF_LP(float, 2, 6) HF_LP(float, 2, 8)
-    }
+    HF_LP(128, float, 1, 1, 2) HF_LP(256, float, 1, 2, 4) HF_LP(384, float, 1, 3, 6) HF_LP(512, float, 1, 4, 8)
+    HF_LP(768, float, 1, 6, 12) HF_LP(1024, float, 1, 8, 16)
+    HF_LP(128, float, 2, 1, 2) HF_LP(256, float, 2, 1, 4) HF_LP(384, float, 2, 2, 6) HF_LP(512, float, 2, 2, 8)
+    HF_LP(768, float, 2, 3, 12) HF_LP(1024, float, 2, 4, 16)
   }
 #undef HF_LP
-  if (!kern || d % 32 != 0) {
+  if (!kern) {
     set_error("precision form needs d in {128, 256, 384, 512, 768, 1024} (got %d)", d);
     return HF_ERR_UNSUPPORTED;
   }
-  if (smem > 64 * 1024) HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  if (smem + 1024 > 64 * 1024) HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   const void* Xp = f->X_pos;
   const void* Xlp = prec == HF_PREC_BF16 ? f->X_bf16 : f->X_fp8;
   const float* s8 = f->s_fp8;

@@ -109,11 +109,14 @@ __global__ __launch_bounds__(256) void k_descend_lds(const uint32_t* __restrict_
 // equal sign rows need the deeper levels: such (query, tree) pairs are
 // listed for the wavefront-per-pair kernel that computes full keys.
 constexpr int RK_T = 256;
-template <int NW>
-__device__ __forceinline__ int cmp_top(const uint32_t* sq, const uint32_t* sp, const uint16_t* ax, int d,
-                                       int* jstar) {
-  uint32_t par = 0;
-  for (int i = 0; i < d; ++i) {
+// Compares the query's and a point's top key levels from tree position
+// `start` on, `par` being the query's prefix parity before it (both agree
+// before `start`).  *par_at (if c_at >= start) receives the parity before
+// position c_at.
+__device__ __forceinline__ int cmp_top(const uint32_t* sq, const uint32_t* sp, const uint16_t* ax, int d, int start,
+                                       uint32_t par, int* jstar, int c_at, uint32_t* par_at) {
+  for (int i = start; i < d; ++i) {
+    if (i == c_at) *par_at = par;
     const uint32_t v = ax[i];
     const uint32_t a = v & 0x7FFFu, w = a >> 5, sh = a & 31u;
     const uint32_t qb = (sq[w * RK_T] >> sh) & 1u, pb = (sp[w * RK_T] >> sh) & 1u;
@@ -166,58 +169,71 @@ __global__ __launch_bounds__(RK_T) void k_rank_top(const uint32_t* __restrict__ 
 #pragma unroll
     for (int w = 0; w < NW; ++w) sp[w * RK_T] = sgn[(int64_t)p * NW + w];
   };
-  // first descent: the leaf and its first point z
-  uint32_t idx = 0, leaf_lo = 0;
+  // descent by node tests to a leaf [lo, hi); b_last = split bit of its parent
+  uint32_t idx = 0;
+  int64_t lo = 0, hi = N;
+  int b_last = -1;
   for (int step = 0; step < max_steps; ++step) {
     const uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
-    if (r.y >> 31) {
-      leaf_lo = r.x;
-      break;
+    const uint2 sb = *(const uint2*)(au + 2 * (int64_t)idx);  // {m, b} or {lo, NONE}
+    if (r.y >> 31) break;
+    b_last = (int)sb.y;
+    if (test(r.y)) {
+      lo = sb.x;
+      idx = r.x;
+    } else {
+      hi = sb.x;
+      idx = idx + 1u;
     }
-    idx = test(r.y) ? r.x : idx + 1u;
   }
-  load_row(tp[leaf_lo]);
+  // the leaf's first point z: the query agrees with it before key bit j*
+  load_row(tp[lo]);
   int jstar = 0;
-  int c = cmp_top<NW>(sq, sp, ax, d, &jstar);
+  uint32_t par0 = 0;
+  const int c0 = b_last + 1;  // every key of the leaf agrees with z before c0
+  const int c = cmp_top(sq, sp, ax, d, 0, 0u, &jstar, c0, &par0);
   bool need_deep = c == 0;
   int64_t rank = -1;
-  if (!need_deep) {
-    int64_t lo = 0, hi = N;
+  if (!need_deep && jstar < b_last) {
+    // the query leaves the path above the leaf: the first node whose split
+    // bit lies beyond j* holds it entirely before (bit 0) or after (bit 1)
+    int64_t l2 = 0, h2 = N;
     idx = 0;
     for (int step = 0; step < max_steps; ++step) {
       const uint2 r = *(const uint2*)(nd + 2 * (int64_t)idx);
-      if (r.y >> 31) break;
-      const uint2 sb = *(const uint2*)(au + 2 * (int64_t)idx);  // {m, b}
-      if ((int64_t)sb.y > jstar) {
-        rank = c > 0 ? hi : lo;
+      const uint2 sb = *(const uint2*)(au + 2 * (int64_t)idx);
+      if ((int)sb.y > jstar) {
+        rank = c > 0 ? h2 : l2;
         break;
       }
       if (test(r.y)) {
-        lo = sb.x;
+        l2 = sb.x;
         idx = r.x;
       } else {
-        hi = sb.x;
+        h2 = sb.x;
         idx = idx + 1u;
       }
     }
-    if (rank < 0) {  // inside the leaf [lo, hi): lower bound by key
-      int64_t a = lo, b = hi;
-      while (a < b) {
-        const int64_t mid = (a + b) >> 1;
-        load_row(tp[mid]);
-        int j2;
-        const int c2 = cmp_top<NW>(sq, sp, ax, d, &j2);
-        if (c2 == 0) {
-          need_deep = true;
-          break;
-        }
-        if (c2 > 0)
-          a = mid + 1;
-        else
-          b = mid;
+  } else if (!need_deep) {
+    // inside the leaf: the query and every key of the leaf agree before c0,
+    // so comparisons start there from the query's parity before c0
+    int64_t a = lo, b = hi;
+    while (a < b) {
+      const int64_t mid = (a + b) >> 1;
+      load_row(tp[mid]);
+      int j2;
+      uint32_t unused;
+      const int c2 = cmp_top(sq, sp, ax, d, c0, par0, &j2, -1, &unused);
+      if (c2 == 0) {
+        need_deep = true;
+        break;
       }
-      rank = a;
+      if (c2 > 0)
+        a = mid + 1;
+      else
+        b = mid;
     }
+    rank = a;
   }
   if (need_deep) {
     const uint32_t slot = atomicAdd(ndeep, 1u);
@@ -778,6 +794,8 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     StageTimer tm(ST_QSKETCH, s);
     if (f->sketch_kind == HF_SKETCH_LEARNED)
       HF_TRY(lhash_encode_dev(f->lhash, Q, f->dtype, nq, qsk, s, &ws));
+    else if (f->sketch_kind == HF_SKETCH_SIGN)
+      HF_TRY(sign_sketch(Q, f->dtype, nq, d, qsk, s));
     else
       HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws, f->srp_R));
   }
@@ -910,6 +928,10 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     if (p.precision == HF_PREC_FP32) {
       StageTimer tm(ST_RERANK, s);
       HF_TRY(rerank(q0, nb));
+    } else if (p.precision == HF_PREC_C4) {
+      StageTimer tm(ST_RERANK, s);
+      HF_TRY(rerank_c4_launch(f, (const char*)Q + q0 * d * esz, nb, c2 + q0 * k2, c2n + q0, k2, (int)p.h,
+                              (int)p.k, ids + q0 * p.k, scores + q0 * p.k, en_out ? en_out + q0 : nullptr, s));
     } else {
       StageTimer tm(ST_LOWPREC, s);
       const int S = (int)(p.survivors ? p.survivors : 4 * p.k);

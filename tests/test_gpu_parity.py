@@ -282,6 +282,76 @@ def test_exact_position_small_and_ragged(hf, orc):
     _exact_case(hf, orc, x, q, T=2, M=50, seed=11, sk_seed=12, params=[(40, 30, 0, 5)])
 
 
+def _c4_case(hf, orc, x, q, T, M, seed, params, position="leaf"):
+    """The compressed layout against the oracle: sign sketches bit for bit,
+    window starts and C2 exact, scores from the 4-bit codes within TOL of the
+    oracle's FP64 scores of the same codes, ids equal up to near-ties."""
+    F = orc.build_forest(x, T=T, M=M, seed=seed, sketch_seed=1)
+    fo = hf.Forest(dev(x), n_trees=T, leaf_max=M, seed=seed, sketch_seed=1, sketch="sign")
+    sg, mag, sc = orc.c4_encode(x)
+    want_sk = np.zeros((x.shape[0], 8), np.uint64)
+    want_sk[:, :sg.shape[1]] = sg
+    assert (fo.sketches().cpu().numpy().view(np.uint64) == want_sk[F["pos2id"]]).all()
+    fo.add_precision("c4")
+    dec = np.where(x >= 0, 1.0, -1.0) * (mag + 0.5) * sc[:, None]  # decoded rows, FP64
+    Q = q.astype(np.float64)
+    for (k1, k2, h, k) in params:
+        want = orc.search_c4(F, q, k1, k2, h, k, position=position)
+        r = fo.search_debug(dev(q), k, k1, k2, h, precision="c4", position=position)
+        assert (u32(r["winstart"]) == want["winstart"]).all()
+        assert (u32(r["c2"]) == want["c2"]).all()
+        assert (r["en"].cpu().numpy() == want["en"]).all()
+        gi, gs = r["ids"].cpu().numpy(), r["scores"].cpu().numpy()
+        fin = np.isfinite(want["scores"])
+        assert (np.isfinite(gs) == fin).all()
+        assert np.abs(gs[fin] - want["scores"][fin]).max() <= TOL
+        for i in range(gi.shape[0]):
+            v = gi[i][gi[i] >= 0]
+            assert np.unique(v).size == v.size
+            kth = want["scores"][i, k - 1]
+            for c in set(gi[i].tolist()) ^ set(want["ids"][i].tolist()):
+                assert c >= 0 and abs(float(Q[i] @ dec[c]) - kth) <= TOL
+    fo.free()
+
+
+def test_compressed_layout_parity(hf, orc):
+    """Section 3.1's layout: 384-bit coordinate-sign sketches, 4-bit codes
+    sharing the sign bit, rerank from the codes with unquantized queries."""
+    x, q = datagen.mixture(20000, 384, 64, 0.05, 76, dtype=np.float16, query_seed=77, nq=100)
+    _c4_case(hf, orc, x, q, T=4, M=100, seed=21, params=[(300, 100, 2, 30), (50, 40, 0, 10)])
+    _c4_case(hf, orc, x, q[:40].copy(), T=4, M=100, seed=21, params=[(300, 100, 1, 30)], position="exact")
+
+
+def test_compressed_layout_small_dims(hf, orc):
+    w = datagen.WORKLOADS["search-10Kx32"]
+    x, q = datagen.mixture(w["n"], w["d"], w["n_comp"], w["sigma"], w["seed"], unit=w["unit"],
+                           dtype=np.float32, query_seed=w["query_seed"], nq=200)
+    _c4_case(hf, orc, x, q, T=8, M=100, seed=1, params=[(256, 64, 1, 10)])
+    x, q = datagen.mixture(3001, 70, 7, 0.1, 78, unit=False, dtype=np.float32, nq=50)
+    x[5] = 0.0  # a zero row: scale 0, every value 0
+    _c4_case(hf, orc, x, q, T=3, M=20, seed=9, params=[(120, 60, 1, 8)])
+
+
+def test_forest_built_with_learned_or_sign_sketches(hf, orc):
+    """hf_build_forest with the learned hash or sign sketches gives the same
+    forest as building with SRP and switching the sketches afterwards."""
+    x, q = datagen.mixture(5000, 384, 16, 0.05, 79, dtype=np.float16, query_seed=80, nq=50)
+    L = hf.LHash(*_net(81))
+    a = hf.Forest(dev(x), n_trees=3, leaf_max=50, seed=2, sketch_seed=3, sketch="learned", lhash=L)
+    b = hf.Forest(dev(x), n_trees=3, leaf_max=50, seed=2, sketch_seed=3)
+    b.set_sketch("learned", L)
+    assert (a.sketches().cpu().numpy() == b.sketches().cpu().numpy()).all()
+    ia, _ = a.search(dev(q), 10, 200, 60, 1)
+    ib, _ = b.search(dev(q), 10, 200, 60, 1)
+    assert (ia.cpu().numpy() == ib.cpu().numpy()).all()
+    c = hf.Forest(dev(x), n_trees=3, leaf_max=50, seed=2, sketch_seed=3, sketch="sign")
+    b.set_sketch("sign")
+    assert (c.sketches().cpu().numpy() == b.sketches().cpu().numpy()).all()
+    for f in (a, b, c):
+        f.free()
+    L.free()
+
+
 def test_forest_search_tree_subset(hf, orc):
     """Searching trees 0..n-1 of a larger forest equals the search of a forest
     of those trees (tree t does not depend on how many trees follow it)."""
@@ -590,6 +660,28 @@ def test_lhash_gradients_match_oracle(hf, orc):
         worst = np.max(np.abs(gg - oo) / lim)
         print("gradient %s: worst |diff| / bound = %.3g" % (name, worst))
         assert (np.abs(gg - oo) <= lim).all(), (name, worst)
+    L.free()
+
+
+def test_lhash_gradients_with_hard_negatives(hf, orc):
+    """The objective with one hard negative per query: loss and every gradient
+    entry against the FP64 oracle (same bound as without negatives)."""
+    W = _net(95)
+    c = datagen.centres(384, 16, 96, True)
+    A = datagen.draw(c, 80, 0.05, 97, np.float16)
+    B = datagen.draw(c, 80, 0.05, 98, np.float16)
+    Nn = datagen.draw(c, 80, 0.05, 99, np.float16)
+    tp = hf.train_params(slope=2.0, tau=0.2, balance=0.05)
+    L = hf.LHash(*W)
+    loss, g = L.grad(dev(A), dev(B), tp, N=dev(Nn))
+    oloss, og = orc.lhash_grad(A, B, *W, slope=2.0, tau=0.2, lam=0.05, rounded=True, Neg=Nn)
+    assert abs(loss - oloss) <= 1e-4 * max(1.0, abs(oloss))
+    RTOL, ATOL = 1e-4, 1e-5
+    for name, gg, oo in zip(["W1", "b1", "W2", "b2"], g, og):
+        gg = gg.cpu().numpy().astype(np.float64).reshape(oo.shape)
+        lim = RTOL * np.abs(oo) + ATOL * np.abs(oo).max()
+        print("gradient %s with negatives: worst |diff| / bound = %.3g" % (name, np.max(np.abs(gg - oo) / lim)))
+        assert (np.abs(gg - oo) <= lim).all(), name
     L.free()
 
 

@@ -811,3 +811,46 @@ def test_c4_search_c2_by_sign_hamming(orc):
         qs = sgn(q[i])
         want = sorted(C1, key=lambda p: (bin(qs ^ sgn(X[p])).count("1"), p))[:k2]
         assert r["c2"][i][:len(want)].tolist() == want
+
+
+def test_lhash_gradients_with_hard_negatives_match_finite_differences(orc):
+    """The objective with one hard negative per query (an extra logit in each
+    query's softmax) has the gradients the central finite differences give."""
+    W1, b1, W2, b2 = _small_net(13)
+    rng = np.random.default_rng(14)
+    A = rng.standard_normal((5, 24)).astype(np.float32)
+    B = (A + 0.3 * rng.standard_normal((5, 24))).astype(np.float32)
+    N = (A + 0.6 * rng.standard_normal((5, 24))).astype(np.float32)
+    args = dict(slope=2.0, tau=0.2, lam=0.05, rounded=False, Neg=N)
+    loss, g = orc.lhash_grad(A, B, W1, b1, W2, b2, **args)
+    loss0, _ = orc.lhash_grad(A, B, W1, b1, W2, b2, slope=2.0, tau=0.2, lam=0.05, rounded=False)
+    assert loss != loss0  # the negative enters the loss
+    params = [W1, b1, W2, b2]
+    for pi, P in enumerate(params):
+        flat = P.reshape(-1)
+        for idx in rng.choice(flat.size, 5, replace=False):
+            h = 1e-4  # well inside the relu kinks of this batch (the nearest pre-activation is 3e-4 from 0)
+            old = flat[idx]
+            vals = []
+            for sgn in (+1, -1):
+                flat[idx] = old + sgn * h
+                vals.append(orc.lhash_grad(A, B, *params, **args)[0])
+            flat[idx] = old
+            num = (vals[0] - vals[1]) / (np.float64(np.float32(old + h)) - np.float64(np.float32(old - h)))
+            ana = g[pi].reshape(-1)[idx]
+            assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)) + 1e-7, (pi, idx, num, ana)
+
+
+def test_lhash_loss_with_negatives_closed_form(orc):
+    """With all weights zero every code is 0: every logit is 0, so the loss is
+    log(B + 1) with a negative per query (log B without) and all gradients of
+    W1 and W2 vanish."""
+    d, hid, Bn = 6, 4, 5
+    W1, b1 = np.zeros((hid, d), np.float32), np.zeros(hid, np.float32)
+    W2, b2 = np.zeros((512, hid), np.float32), np.zeros(512, np.float32)
+    A = np.random.default_rng(15).standard_normal((Bn, d)).astype(np.float32)
+    loss, g = orc.lhash_grad(A, A, W1, b1, W2, b2, 1.0, 0.5, 0.1, rounded=False, Neg=A)
+    assert abs(loss - np.log(Bn + 1)) < 1e-12
+    loss2, _ = orc.lhash_grad(A, A, W1, b1, W2, b2, 1.0, 0.5, 0.1, rounded=False)
+    assert abs(loss2 - np.log(Bn)) < 1e-12
+    assert np.abs(g[0]).max() == 0 and np.abs(g[2]).max() == 0

@@ -137,7 +137,7 @@ hf_status data_exp(const void* X, hf_dtype dt, int64_t n, int32_t want, int* e, 
 void forest_release(hf_forest* f) {
   if (!f) return;
   void* ptrs[] = {f->X_pos, f->sk_pos, f->pos2id, f->tree_perm, f->nodes, f->curve_perm, f->curve_refl,
-                  f->X_bf16, f->X_fp8, f->s_fp8, f->node_off_dev, f->srp_R, f->node_aux, f->sgn_pos,
+                  f->X_bf16, f->X_fp8, f->s_fp8, f->node_off_dev, f->srp_R, f->srp_Rb, f->node_aux, f->sgn_pos,
                   f->c4_mag, f->c4_scale};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -431,12 +431,18 @@ hf_status hf_build_forest(const void* X_dev, hf_dtype dtype, int64_t N, int32_t 
   HF_LAUNCH_CHECK();
   size_t r_bytes = 0;
   HF_TRY(srp_matrix_upload(d, params->sketch_seed, &f->srp_R, &r_bytes, s));
+  if (d % 16 == 0) {
+    HF_TRY(srp_matrix_i8_upload(d, params->sketch_seed, &f->srp_Rb, s));
+    r_bytes += 512 * (size_t)d;
+  }
   {
     StageTimer tm(ST_BSKETCH, s);
     if (params->sketch == HF_SKETCH_LEARNED)
       HF_TRY(lhash_encode_dev(params->lhash, f->X_pos, dtype, N, f->sk_pos, s));
     else if (params->sketch == HF_SKETCH_SIGN)
       HF_TRY(sign_sketch(f->X_pos, dtype, N, d, f->sk_pos, s));
+    else if (f->srp_Rb && getenv("HF_SRP_VALU") == nullptr)
+      HF_TRY(srp_sketch_mfma(f->X_pos, dtype, N, d, e, f->srp_Rb, f->sk_pos, s));
     else
       HF_TRY(srp_sketch(f->X_pos, dtype, N, d, e, params->sketch_seed, f->sk_pos, ws, f->srp_R));
   }
@@ -592,6 +598,8 @@ hf_status hf_forest_set_sketch(hf_forest* f, hf_sketch_kind kind, const hf_lhash
     HF_TRY(lhash_encode_dev(lhash, f->X_pos, f->dtype, f->N, f->sk_pos, s));
   } else if (kind == HF_SKETCH_SIGN) {
     HF_TRY(sign_sketch(f->X_pos, f->dtype, f->N, f->d, f->sk_pos, s));
+  } else if (f->srp_Rb && getenv("HF_SRP_VALU") == nullptr) {
+    HF_TRY(srp_sketch_mfma(f->X_pos, f->dtype, f->N, f->d, f->e, f->srp_Rb, f->sk_pos, s));
   } else {
     Workspace ws(s);
     HF_TRY(srp_sketch(f->X_pos, f->dtype, f->N, f->d, f->e, f->sketch_seed, f->sk_pos, ws, f->srp_R));

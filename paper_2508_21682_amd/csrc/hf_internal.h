@@ -263,6 +263,11 @@ hf_status build_trie(const uint8_t* codes, int64_t N, int d, int M, const int32_
 // else it is generated from sketch_seed, uploaded and waited for
 hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64_t sketch_seed,
                      uint64_t* out, Workspace& ws, const uint64_t* R_dev = nullptr);
+// the same sketches on the int8 matrix cores (d a multiple of 16), with the
+// projection signs as 512 x d int8 rows (srp_matrix_i8_upload, hipMalloc)
+hf_status srp_sketch_mfma(const void* X, hf_dtype dt, int64_t N, int d, int e, const int8_t* Rb, uint64_t* out,
+                          hipStream_t s);
+hf_status srp_matrix_i8_upload(int d, uint64_t sketch_seed, int8_t** out, hipStream_t s);
 // the projection matrix of (d, sketch_seed) in a new device buffer (hipMalloc)
 hf_status srp_matrix_upload(int d, uint64_t sketch_seed, uint64_t** out, size_t* bytes, hipStream_t s);
 // stage timing (hf_api.hip): events around a launch when timing is on
@@ -350,6 +355,7 @@ struct hf_forest {
   std::vector<int64_t> node_off;  // T+1 offsets (in nodes)
   int64_t* node_off_dev; // the same offsets on the device
   uint64_t* srp_R;       // SRP projection matrix of (d, sketch_seed) on the device
+  int8_t* srp_Rb;        // the same signs as 512 x d int8 rows (matrix-core sketches), or null
   int32_t* curve_perm;   // T x d
   uint8_t* curve_refl;   // T x d
   void* X_bf16;          // N x d bfloat16 copy of X_pos (precision form), or null

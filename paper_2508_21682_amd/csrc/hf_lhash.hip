@@ -146,6 +146,170 @@ __global__ __launch_bounds__(256) void k_mlp(const T* __restrict__ A, int64_t M,
   }
 }
 
+// Encoder: both layers fused, 64 rows per workgroup.  The rows (as BF16),
+// then in the same LDS their hidden activations, stay on chip; each
+// wavefront computes a quarter of the columns of a layer for all 64 rows, so
+// a weight element is read once per workgroup (from L2, as the B operand of
+// v_mfma_f32_16x16x32_bf16).  The 512 output signs of each row are gathered
+// with ballots into an LDS bit array and stored as 8 words.  D: input
+// dimension (multiple of 32); HID: hidden units (multiple of 64).  The sums
+// run in the same order as the two-kernel path, so the sketches are equal.
+constexpr int FM_ROWS = 64;
+
+// 8 values of T as BF16, from the raw bytes of one (half) or two (float) uint4
+template <class T>
+__device__ __forceinline__ uint4 raw_to_bf16(uint4 r0, uint4 r1) {
+  float f[8];
+  if constexpr (sizeof(T) == 2) {
+    const __half2* h = (const __half2*)&r0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float2 v = __half22float2(h[j]);
+      f[2 * j] = v.x;
+      f[2 * j + 1] = v.y;
+    }
+  } else {
+    const float* a = (const float*)&r0;
+    const float* b = (const float*)&r1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      f[j] = a[j];
+      f[4 + j] = b[j];
+    }
+  }
+  uint4 o;
+  o.x = bf16_rne(f[0]) | (bf16_rne(f[1]) << 16);
+  o.y = bf16_rne(f[2]) | (bf16_rne(f[3]) << 16);
+  o.z = bf16_rne(f[4]) | (bf16_rne(f[5]) << 16);
+  o.w = bf16_rne(f[6]) | (bf16_rne(f[7]) << 16);
+  return o;
+}
+
+// One dense layer on the 64 rows held in LDS (row stride AS, K inputs):
+// wavefront wv computes columns [wv NC 16, (wv + 1) NC 16) into acc.  The
+// weight fragments of step k + 32 are loaded while step k's products run.
+template <int K, int NC>
+__device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ sa, int AS, const uint16_t* __restrict__ W,
+                                            int wv, int ri, int g, float4v (&acc)[4][NC]) {
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) acc[rt][cb] = (float4v){0.f, 0.f, 0.f, 0.f};
+  const uint16_t* wp = W + (int64_t)(wv * NC * 16 + ri) * K + 8 * g;
+  uint4 bw[NC], bn[NC];
+#pragma unroll
+  for (int cb = 0; cb < NC; ++cb) bw[cb] = *(const uint4*)(wp + (int64_t)cb * 16 * K);
+#pragma unroll
+  for (int k = 0; k < K; k += 32) {
+    if (k + 32 < K) {
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) bn[cb] = *(const uint4*)(wp + (int64_t)cb * 16 * K + k + 32);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const uint4 a = *(const uint4*)(sa + (16 * rt + ri) * AS + k + 8 * g);
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb)
+        acc[rt][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                              __builtin_bit_cast(bf16x8, bw[cb]), acc[rt][cb], 0, 0, 0);
+    }
+    if (k + 32 < K) {
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) bw[cb] = bn[cb];
+    }
+  }
+}
+
+// Encoder: both layers fused, 64 rows per workgroup.  The rows (as BF16),
+// then in the same LDS their hidden activations, stay on chip; each
+// wavefront computes a quarter of the columns of a layer for all 64 rows, so
+// a weight element is read once per workgroup (from L2, as the B operand of
+// v_mfma_f32_16x16x32_bf16).  The 512 output signs of each row are gathered
+// with ballots into an LDS bit array and stored as 8 words.  D: input
+// dimension (multiple of 32); HID: hidden units (multiple of 64).  The sums
+// run in the same order as the two-kernel path, so the sketches are equal.
+template <class T, int D, int HID>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_fused(
+    const T* __restrict__ X, int64_t M, const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+    const uint16_t* __restrict__ W2, const float* __restrict__ b2, uint64_t* __restrict__ SK) {
+  constexpr int XS = D + 8, HS = HID + 8;  // padded row strides (bf16 elements)
+  constexpr int XH = FM_ROWS * (XS > HS ? XS : HS);
+  // the hidden activations overwrite the rows once layer 1 has read them
+  __shared__ __align__(16) uint16_t s_xh[XH];
+  __shared__ __align__(16) uint16_t s_bits[FM_ROWS * 32];
+  uint16_t* const s_x = s_xh;
+  uint16_t* const s_h = s_xh;
+  const int wv = threadIdx.x / 64, l = __lane_id(), ri = l % 16, g = l / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * FM_ROWS;
+  // stage the rows as BF16 (zero rows past M): every load of a batch is in
+  // flight before the first conversion
+  constexpr int PER = FM_ROWS * (D / 8) / 256, BATCH = sizeof(T) == 2 ? PER : PER / 2;
+  static_assert(PER * 256 == FM_ROWS * (D / 8) && PER % BATCH == 0, "staging shape");
+#pragma unroll
+  for (int b0 = 0; b0 < PER; b0 += BATCH) {
+    uint4 raw[BATCH][2];
+#pragma unroll
+    for (int i = 0; i < BATCH; ++i) {
+      const int e = threadIdx.x + 256 * (b0 + i), r = e / (D / 8), c8 = e % (D / 8);
+      const int64_t row = r0 + r < M ? r0 + r : M - 1;
+      const T* p = X + row * D + 8 * c8;
+      raw[i][0] = *(const uint4*)p;
+      raw[i][1] = sizeof(T) == 2 ? make_uint4(0, 0, 0, 0) : *(const uint4*)(p + 4);
+    }
+#pragma unroll
+    for (int i = 0; i < BATCH; ++i) {
+      const int e = threadIdx.x + 256 * (b0 + i), r = e / (D / 8), c8 = e % (D / 8);
+      uint4 v = raw_to_bf16<T>(raw[i][0], raw[i][1]);
+      if (r0 + r >= M) v = make_uint4(0, 0, 0, 0);
+      *(uint4*)(s_x + r * XS + 8 * c8) = v;
+    }
+  }
+  __syncthreads();
+  // layer 1: wavefront wv computes hidden units [wv HID/4, (wv+1) HID/4) for the 64 rows
+  {
+    constexpr int NC = HID / 4 / 16;
+    float4v acc[4][NC];
+    fused_layer<D, NC>(s_x, XS, W1, wv, ri, g, acc);
+    __syncthreads();  // every wavefront is done with the rows
+    // bias, relu, BF16: lane holds rows 4 g + r of row tile rt, column ri of tile cb
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+      const int c = wv * (HID / 4) + cb * 16 + ri;
+      const float bc = b1[c];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float v = acc[rt][cb][r] + bc;
+          s_h[(16 * rt + 4 * g + r) * HS + c] = (uint16_t)bf16_rne(v > 0.f ? v : 0.f);
+        }
+    }
+  }
+  __syncthreads();
+  // layer 2: wavefront wv computes outputs [128 wv, 128 wv + 128) for the 64 rows
+  {
+    float4v acc[4][8];
+    fused_layer<HID, 8>(s_h, HS, W2, wv, ri, g, acc);
+    // the ballot's bits 16 g' + i: row 16 rt + 4 g' + r, output 128 wv + 16 cb + i
+#pragma unroll
+    for (int cb = 0; cb < 8; ++cb) {
+      const float bc = b2[wv * 128 + cb * 16 + ri];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint64_t m = __ballot(acc[rt][cb][r] + bc >= 0.f);
+          if (l < 4) s_bits[(16 * rt + 4 * l + r) * 32 + 8 * wv + cb] = (uint16_t)(m >> (16 * l));
+        }
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < FM_ROWS * 8; e += 256) {
+    const int r = e / 8, w = e % 8;
+    if (r0 + r < M) SK[(r0 + r) * 8 + w] = *(const uint64_t*)(s_bits + r * 32 + 4 * w);
+  }
+}
+
 // C = alpha * op(A) * op(B) + beta * C, FP32, row-major storage; op(A)[m][k] =
 // A[m*sam + k*sak], op(B)[k][n] = B[k*sbk + n*sbn].  64x64 tiles, 4x4 per thread.
 __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, float alpha, const float* __restrict__ A,
@@ -475,6 +639,16 @@ hf_status check_lhash(const hf_lhash* L) {
 hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_t N, uint64_t* sk, hipStream_t s,
                            Workspace* ext) {
   HF_TRY(check_lhash(L));
+  if (N <= 0) return HF_OK;
+  if (L->d == 384 && L->hid == 256 && getenv("HF_MLP_UNFUSED") == nullptr) {
+    const unsigned grid = (unsigned)ceil_div(N, FM_ROWS);
+    if (dt == HF_F16)
+      k_mlp_fused<__half, 384, 256><<<grid, 256, 0, s>>>((const __half*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
+    else
+      k_mlp_fused<float, 384, 256><<<grid, 256, 0, s>>>((const float*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
+    HF_LAUNCH_CHECK();
+    return HF_OK;
+  }
   Workspace own(s);
   Workspace& ws = ext ? *ext : own;
   const int64_t chunk = std::min<int64_t>(N, 1 << 20);

@@ -352,6 +352,23 @@ def test_forest_built_with_learned_or_sign_sketches(hf, orc):
     L.free()
 
 
+def test_srp_matrix_core_sketches(hf, orc, monkeypatch):
+    """Forest sketches from the int8 matrix-core kernel (d a multiple of 16,
+    here with a partial 64-coordinate step and a ragged last block of rows)
+    equal the oracle's and the vector-ALU kernel's, bit for bit."""
+    for d, dtype in ((80, np.float32), (384, np.float16)):
+        x = datagen.mixture(4000 + 37, d, 9, 0.1, 83, unit=False, dtype=dtype)
+        F = orc.build_forest(x, T=1, M=50, seed=4, sketch_seed=5)
+        a = hf.Forest(dev(x), n_trees=1, leaf_max=50, seed=4, sketch_seed=5)
+        got = a.sketches().cpu().numpy().view(np.uint64)
+        assert (got == F["sk_pos"]).all(), "d=%d" % d
+        monkeypatch.setenv("HF_SRP_VALU", "1")
+        a.set_sketch("srp")
+        assert (a.sketches().cpu().numpy().view(np.uint64) == got).all(), "d=%d" % d
+        monkeypatch.delenv("HF_SRP_VALU")
+        a.free()
+
+
 def test_forest_search_tree_subset(hf, orc):
     """Searching trees 0..n-1 of a larger forest equals the search of a forest
     of those trees (tree t does not depend on how many trees follow it)."""
@@ -631,6 +648,20 @@ def test_lhash_encode_parity(hf, orc, dtype, n):
     firm = np.abs(z2) > band
     assert firm.mean() > 0.99
     assert (gbits[firm] == (z2[firm] >= 0)).all()
+    L.free()
+
+
+def test_lhash_fused_encoder_matches_two_kernel_path(hf, monkeypatch):
+    """The fused two-layer encoder sums in the two-kernel path's order, so the
+    sketches agree bit for bit (ragged last block of 64 rows, both dtypes)."""
+    L = hf.LHash(*_net(96))
+    for dtype, n in ((np.float16, 1000 + 37), (np.float32, 70)):
+        x = datagen.mixture(n, 384, 8, 0.05, 97, dtype=dtype)
+        a = L.encode(dev(x)).cpu().numpy()
+        monkeypatch.setenv("HF_MLP_UNFUSED", "1")
+        b = L.encode(dev(x)).cpu().numpy()
+        monkeypatch.delenv("HF_MLP_UNFUSED")
+        assert (a == b).all()
     L.free()
 
 

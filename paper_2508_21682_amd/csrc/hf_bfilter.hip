@@ -53,16 +53,6 @@ struct EntryMap {
   }
 };
 
-__device__ __forceinline__ uint32_t ham64(const uint4* a, const uint4* b) {
-  uint32_t h = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const uint4 x = a[i], y = b[i];
-    h += __popc(x.x ^ y.x) + __popc(x.y ^ y.y) + __popc(x.z ^ y.z) + __popc(x.w ^ y.w);
-  }
-  return h;
-}
-
 // Threshold per query from the trees t = j * tstride, j < Ts: the smallest h
 // whose sampled count reaches need_s + 3 sqrt(need_s) + 1 (need_s = the wanted
 // count scaled to the sample), 512 (every entry passes) if none does.
@@ -73,31 +63,29 @@ __global__ __launch_bounds__(BF_T) void k_tau(const uint32_t* __restrict__ tree_
   __shared__ uint32_t h[HBINS + 1];
   const int64_t q = blockIdx.x;
   for (int i = threadIdx.x; i <= HBINS; i += BF_T) h[i] = 0;
-  uint4 qs[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) qs[i] = ((const uint4*)(qsk + q * 8))[i];
-  __syncthreads();
   const uint32_t total = (uint32_t)Ts * (uint32_t)len;
-  constexpr int U = 4;
-  for (uint32_t e0 = threadIdx.x; e0 < total; e0 += BF_T * U) {
-    uint32_t p[U];
+  // four lanes per entry, each on 16 bytes of its sketch (one 64-byte run)
+  constexpr int R = 8;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, qd = lane >> 2, part = lane & 3;
+  const uint4 qp = ((const uint4*)(qsk + q * 8))[part];
+  __syncthreads();
+  for (uint32_t e0 = 16u * R * wv; e0 < total; e0 += 16u * R * (BF_T / 64)) {
+    uint4 sv[R];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      uint32_t e = e0 + u * BF_T;
+    for (int u = 0; u < R; ++u) {
+      uint32_t e = e0 + 16u * u + qd;
       e = e < total ? e : total - 1u;
       const uint32_t j = e / (uint32_t)len, i = e - j * (uint32_t)len;
       const int64_t t = (int64_t)j * tstride;
-      p[u] = tree_perm[t * N + win[q * T + t] + i];
+      const uint32_t p = tree_perm[t * N + win[q * T + t] + i];
+      sv[u] = ((const uint4*)(sk + (int64_t)p * 8))[part];
     }
-    uint4 s[U][4];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) s[u][i] = ((const uint4*)(sk + (int64_t)p[u] * 8))[i];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t hv = ham64(s[u], qs);
-      atomicAdd(&h[e0 + u * BF_T < total ? hv : (uint32_t)HBINS], 1u);
+    for (int u = 0; u < R; ++u) {
+      uint32_t hv = __popc(sv[u].x ^ qp.x) + __popc(sv[u].y ^ qp.y) + __popc(sv[u].z ^ qp.z) + __popc(sv[u].w ^ qp.w);
+      hv += (uint32_t)__shfl_xor((int)hv, 1);
+      hv += (uint32_t)__shfl_xor((int)hv, 2);
+      if (part == 0 && e0 + 16u * u + qd < total) atomicAdd(&h[hv], 1u);
     }
   }
   __syncthreads();
@@ -129,7 +117,7 @@ __global__ __launch_bounds__(BF_T) void k_bcount(EntryMap em, int T, const uint3
   if (threadIdx.x == 0) ccnt[q] = 0;
   __syncthreads();
   const uint32_t total = (uint32_t)T * (uint32_t)em.len;
-  constexpr int U = 4;
+  constexpr int U = 16;  // position loads in flight per thread
   for (uint32_t e0 = threadIdx.x; e0 < total; e0 += BF_T * U) {
     uint32_t p[U];
 #pragma unroll
@@ -208,13 +196,15 @@ __global__ __launch_bounds__(BS_T) void k_bplan(const uint32_t* __restrict__ tot
 // The query's entries go through LDS SC_CH at a time, counting-sorted by
 // bucket, so that consecutive lanes store consecutive records of one run
 // instead of one scattered 4-byte store per entry.
-constexpr int SC_T = 1024, SC_PER = 16, SC_CH = SC_T * SC_PER;
+constexpr int SC_PER = 16;
+template <int SC_T>
 __global__ __launch_bounds__(SC_T) void k_bscatter(EntryMap em, int T, const uint32_t* __restrict__ win, int bb,
                                                    int nbk, int64_t nb, const uint32_t* __restrict__ cnt,
                                                    const uint32_t* __restrict__ base,
                                                    uint32_t* __restrict__ rec) {
   // nbk next global slots, nbk chunk counts, nbk chunk offsets, T window
   // starts, SC_CH records, SC_CH bucket numbers (16-bit)
+  constexpr int SC_CH = SC_T * SC_PER;
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t scan_tmp[SC_T / 64 + 1];
   uint32_t* gslot = lds;
@@ -272,7 +262,7 @@ __global__ __launch_bounds__(SC_T) void k_bscatter(EntryMap em, int T, const uin
 
 // LDS staging of a chunk's passing entries: appended with LDS atomics while
 // scoring, then flushed with one global atomic per query of the chunk.
-constexpr int QS_MAX = 256;  // queries of a chunk staged in LDS
+constexpr int QS_MAX = 128;  // queries of a chunk staged in LDS
 constexpr int CB = 1024;     // passing entries a chunk stages in LDS
 struct ChunkLds {
   uint4 qs[QS_MAX][4];   // sketches of the chunk's queries
@@ -302,68 +292,94 @@ __device__ __forceinline__ void append_global(bool pass, uint32_t q, uint64_t ke
   }
 }
 
-// Scores records [r0, r1) of one bucket.  STAGED: the chunk's queries
-// q0 .. q0 + QS_MAX - 1 have their sketches and thresholds in LDS, and
-// passing entries are staged in LDS (the global lists directly once CB are).
-template <bool STAGED>
+// Scores records [r0, r1) of one bucket.  Four lanes share a record: lane
+// part j reads bytes 16 j .. 16 j + 15 of the entry's sketch, so the four
+// lanes' loads fall on one 64-byte run (one cache-line access for the
+// record, not one per 16 bytes), and a DPP quad sum gives the distance.  A
+// wavefront takes R rounds of 16 records at a time, every record and sketch
+// load of the R rounds in flight together; no load or store is conditional
+// (past r1 the last record is re-read and its entry cannot pass), so the
+// loads never wait on a branch.  STAGED: the chunk's queries
+// q0 .. q0 + QS_MAX - 1 have their sketches and thresholds in LDS, and the
+// passing entries of a batch are appended to the chunk's LDS list with one
+// atomic per wavefront (the global lists directly once CB are staged).
+template <bool STAGED, int SB>
 __device__ __forceinline__ void score_chunk(const uint32_t* __restrict__ rec, uint32_t r0, uint32_t r1, uint32_t btag,
                                             int bb, const uint64_t* __restrict__ sk,
                                             const uint64_t* __restrict__ qsk, const uint32_t* __restrict__ tau,
                                             ChunkLds& L, uint32_t q0, uint64_t* __restrict__ cand,
                                             uint32_t* __restrict__ ccnt, int capc) {
   const uint32_t pmask = (1u << bb) - 1u;
-  constexpr int U = 4;
-  for (uint32_t ra = r0 + threadIdx.x; ra < r1; ra += BF_T * U) {
-    uint32_t v[U];
+  constexpr int NW = BF_T / 64, R = 4 * SB;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, qd = lane >> 2, part = lane & 3;
+  for (uint32_t rb = r0 + 16u * R * wv; rb < r1; rb += 16u * R * NW) {
+    uint32_t v[R];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t r = ra + u * BF_T;
+    for (int u = 0; u < R; ++u) {
+      const uint32_t r = rb + 16u * u + qd;
       v[u] = rec[r < r1 ? r : r1 - 1u];
     }
-    uint4 sv[U][4];
+    uint4 sv[R];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t p = btag | (v[u] & pmask);
+    for (int u = 0; u < R; ++u) sv[u] = ((const uint4*)(sk + (int64_t)(btag | (v[u] & pmask)) * 8))[part];
+    bool pass[R];
+    uint32_t hvs[R];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sv[u][i] = ((const uint4*)(sk + (int64_t)p * 8))[i];
-    }
-    uint4 qs[U][4];
-    uint32_t tq[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < R; ++u) {
       const uint32_t q = v[u] >> bb;
+      uint4 qs;
+      uint32_t tq;
       if constexpr (STAGED) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) qs[u][i] = L.qs[q - q0][i];
-        tq[u] = L.tau[q - q0];
+        qs = L.qs[q - q0][part];
+        tq = L.tau[q - q0];
       } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) qs[u][i] = ((const uint4*)(qsk + (int64_t)q * 8))[i];
-        tq[u] = tau[q];
+        qs = ((const uint4*)(qsk + (int64_t)q * 8))[part];
+        tq = tau[q];
       }
+      uint32_t hv = __popc(sv[u].x ^ qs.x) + __popc(sv[u].y ^ qs.y) + __popc(sv[u].z ^ qs.z) + __popc(sv[u].w ^ qs.w);
+      hv += quad_perm<QP_XOR1>(hv);
+      hv += quad_perm<QP_XOR2>(hv);
+      hvs[u] = hv;
+      pass[u] = part == 0 && rb + 16u * u + qd < r1 && hv <= tq;
     }
+    if constexpr (STAGED) {
+      // slots of the batch's passing entries: one LDS atomic per wavefront
+      uint64_t m[R];
+      uint32_t tot = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t hv = ham64(sv[u], qs[u]);
-      const uint32_t q = v[u] >> bb, p = btag | (v[u] & pmask);
-      const bool pass = ra + u * BF_T < r1 && hv <= tq[u];
-      const uint64_t key = ((uint64_t)hv << 32) | p;
-      if constexpr (STAGED) {
-        bool direct = false;
-        if (pass) {
-          const uint32_t slot = atomicAdd(&L.nc, 1u);
-          if (slot < (uint32_t)CB) {
-            L.key[slot] = key;
-            L.ql[slot] = (uint16_t)(q - q0);
-            atomicAdd(&L.qc[q - q0], 1u);
-          } else {
-            direct = true;
-          }
-        }
-        if (__ballot(direct)) append_global(direct, q, key, cand, ccnt, capc);
-      } else {
-        append_global(pass, q, key, cand, ccnt, capc);
+      for (int u = 0; u < R; ++u) {
+        m[u] = __ballot(pass[u]);
+        tot += (uint32_t)__popcll(m[u]);
       }
+      if (tot == 0) continue;
+      uint32_t at = 0;
+      if (lane == 0) at = atomicAdd(&L.nc, tot);
+      at = (uint32_t)__shfl((int)at, 0);
+      bool direct[R];
+      bool any_direct = false;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const uint32_t slot = at + (uint32_t)__popcll(m[u] & lanemask_lt());
+        at += (uint32_t)__popcll(m[u]);
+        const uint32_t q = v[u] >> bb;
+        direct[u] = pass[u] && slot >= (uint32_t)CB;
+        any_direct |= direct[u];
+        if (pass[u] && slot < (uint32_t)CB) {
+          L.key[slot] = ((uint64_t)hvs[u] << 32) | (btag | (v[u] & pmask));
+          L.ql[slot] = (uint16_t)(q - q0);
+          atomicAdd(&L.qc[q - q0], 1u);
+        }
+      }
+      if (__ballot(any_direct)) {
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+          append_global(direct[u], v[u] >> bb, ((uint64_t)hvs[u] << 32) | (btag | (v[u] & pmask)), cand, ccnt,
+                        capc);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        append_global(pass[u], v[u] >> bb, ((uint64_t)hvs[u] << 32) | (btag | (v[u] & pmask)), cand, ccnt, capc);
     }
   }
 }
@@ -373,6 +389,7 @@ __device__ __forceinline__ void score_chunk(const uint32_t* __restrict__ rec, ui
 // finite, so every workgroup exits.  Records of a bucket are query-major, so
 // a chunk usually spans few queries: their sketches and thresholds are staged
 // in LDS when at most QS_MAX of them.
+template <int SB>
 __global__ __launch_bounds__(BF_T) void k_bscore(const uint32_t* __restrict__ rec, const uint32_t* __restrict__ base,
                                                  const uint32_t* __restrict__ tot,
                                                  const uint32_t* __restrict__ cumx, int nbx, int bb, uint32_t chunk,
@@ -429,7 +446,7 @@ __global__ __launch_bounds__(BF_T) void k_bscore(const uint32_t* __restrict__ re
           L.qc[i] = 0;
         }
         __syncthreads();
-        score_chunk<true>(rec, r0, r1, btag, bb, sk, qsk, tau, L, q0, cand, ccnt, capc);
+        score_chunk<true, SB>(rec, r0, r1, btag, bb, sk, qsk, tau, L, q0, cand, ccnt, capc);
         __syncthreads();
         // one global atomic per query of the chunk reserves its entries' slots
         for (uint32_t i = threadIdx.x; i < qn; i += BF_T) {
@@ -445,23 +462,45 @@ __global__ __launch_bounds__(BF_T) void k_bscore(const uint32_t* __restrict__ re
           if (slot < (uint32_t)capc) cand[(int64_t)(q0 + ql) * capc + slot] = L.key[i];
         }
       } else {
-        score_chunk<false>(rec, r0, r1, btag, bb, sk, qsk, tau, L, q0, cand, ccnt, capc);
+        score_chunk<false, SB>(rec, r0, r1, btag, bb, sk, qsk, tau, L, q0, cand, ccnt, capc);
       }
       __syncthreads();
     }
   }
 }
 
+// Smallest bin b of h[0..HBINS) whose inclusive prefix sum reaches `want`
+// (HBINS - 1 if none), and the sum of all bins; by the whole workgroup, two
+// bins a thread (BF_SEL_T * 2 >= HBINS).
+__device__ __forceinline__ uint32_t hist_cut(const uint32_t* h, uint32_t want, uint32_t* scan_tmp, uint32_t* s_cut,
+                                             uint32_t* total) {
+  const int b0 = 2 * threadIdx.x, b1 = b0 + 1;
+  const uint32_t c0 = b0 < HBINS ? h[b0] : 0u, c1 = b1 < HBINS ? h[b1] : 0u;
+  if (threadIdx.x == 0) *s_cut = HBINS - 1;
+  const uint32_t ex = block_excl_scan<BF_SEL_T>(c0 + c1, scan_tmp, total);  // has barriers
+  if (ex < want && ex + c0 >= want) atomicMin(s_cut, (uint32_t)b0);
+  else if (ex + c0 < want && ex + c0 + c1 >= want) atomicMin(s_cut, (uint32_t)b1);
+  __syncthreads();
+  return *s_cut;
+}
+
 // C2 of a query from its candidate list, or the query flagged for the
-// entry-by-entry filter.  The keys with distance <= cut, cut chosen from a
-// histogram so that about 1.5 k2 + 64 keys qualify, are sorted first; only
-// when they hold fewer than k2 distinct keys is the whole list sorted.
+// entry-by-entry filter.  The list (at most capc keys) is read once into
+// registers, PER keys a thread.  A key's position is inserted into an LDS hash
+// set (2 capc slots, linear probing): the first insertion of a position marks
+// the distinct key (one position always carries the same distance).  The
+// distinct keys' distance histogram gives the cut at k2 distinct keys; only
+// the distinct keys within the cut are sorted (in the same LDS).  The sorted
+// distinct keys' first k2 are C2 when at least k2 distinct keys passed, or
+// all of them when tau let every entry pass; otherwise the query is flagged.
+template <int PER>
 __global__ __launch_bounds__(BF_SEL_T) void k_bselect(const uint64_t* __restrict__ cand,
                                                       const uint32_t* __restrict__ ccnt,
                                                       const uint32_t* __restrict__ tau, int capc, int k2,
                                                       uint32_t* __restrict__ c2, int32_t* __restrict__ c2n,
                                                       uint32_t* __restrict__ flag) {
-  extern __shared__ uint64_t keys[];  // capc
+  extern __shared__ uint64_t keys[];  // capc keys; first the hash set's 2 capc slots
+  uint32_t* hs = (uint32_t*)keys;
   __shared__ uint32_t hist[HBINS];
   __shared__ uint32_t scan_tmp[BF_SEL_T / 64 + 1];
   __shared__ uint32_t s_cut, s_cnt;
@@ -472,67 +511,69 @@ __global__ __launch_bounds__(BF_SEL_T) void k_bselect(const uint64_t* __restrict
     return;
   }
   const uint64_t* cq = cand + q * capc;
+  uint64_t v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const uint32_t i = threadIdx.x + (uint32_t)j * BF_SEL_T;
+    v[j] = i < n ? cq[i] : ~0ull;
+  }
+  const uint32_t hmask = 2u * (uint32_t)capc - 1u;
+  for (uint32_t i = threadIdx.x; i <= hmask; i += BF_SEL_T) hs[i] = NONE32;
   for (int i = threadIdx.x; i < HBINS; i += BF_SEL_T) hist[i] = 0;
+  if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += BF_SEL_T) atomicAdd(&hist[(uint32_t)(cq[i] >> 32)], 1u);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t want = (uint32_t)k2 + (uint32_t)k2 / 2u + 64u;
-    uint32_t cum = 0, cut = HBINS - 1;
-    for (int h = 0; h < HBINS; ++h) {
-      cum += hist[h];
-      if (cum >= want) {
-        cut = (uint32_t)h;
-        break;
+  uint32_t first = 0;  // bit j: v[j] is its position's first key
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    if (threadIdx.x + (uint32_t)j * BF_SEL_T < n) {
+      const uint32_t pos = (uint32_t)v[j];
+      uint32_t slot = (pos * 0x9E3779B1u) & hmask;
+      for (;;) {  // the set has 2 capc >= 2 n slots, so a free one exists
+        const uint32_t old = atomicCAS(&hs[slot], NONE32, pos);
+        if (old == NONE32) {
+          first |= 1u << j;
+          break;
+        }
+        if (old == pos) break;
+        slot = (slot + 1u) & hmask;
       }
     }
-    s_cut = cut;
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j)
+    if (first >> j & 1u) atomicAdd(&hist[(uint32_t)(v[j] >> 32)], 1u);
+  __syncthreads();
+  uint32_t distinct;
+  const uint32_t cut = hist_cut(hist, (uint32_t)k2, scan_tmp, &s_cut, &distinct);
+  if (distinct < (uint32_t)k2 && tau[q] < HBINS - 1) {
+    if (threadIdx.x == 0) flag[q] = 1;
+    return;
+  }
+  // the hash set is no longer read: its LDS takes the distinct keys within the cut
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const bool take = (first >> j & 1u) && (uint32_t)(v[j] >> 32) <= cut;
+    const uint64_t m = __ballot(take);
+    if (m) {
+      const int lane = threadIdx.x & 63, leader = __ffsll((unsigned long long)m) - 1;
+      uint32_t at = 0;
+      if (lane == leader) at = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+      at = (uint32_t)__shfl((int)at, leader);
+      if (take) keys[at + (uint32_t)__popcll(m & lanemask_lt())] = v[j];
+    }
   }
   __syncthreads();
-  const uint32_t cut0 = s_cut;
-  for (int pass = 0; pass < 2; ++pass) {
-    const uint32_t cut = pass == 0 ? cut0 : (uint32_t)(HBINS - 1);
-    if (pass == 1 && cut0 == cut) break;  // the first pass already took every key
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += BF_SEL_T) {
-      const uint64_t v = cq[i];
-      if ((uint32_t)(v >> 32) <= cut) keys[atomicAdd(&s_cnt, 1u)] = v;
-    }
-    __syncthreads();
-    const int m = (int)s_cnt;
-    int n2 = 1;
-    while (n2 < m) n2 <<= 1;
-    for (int i = m + threadIdx.x; i < n2; i += BF_SEL_T) keys[i] = ~0ull;
-    __syncthreads();
-    bitonic_u64(keys, n2);
-    const int per = (m + BF_SEL_T - 1) / BF_SEL_T;
-    const int a0 = threadIdx.x * per, a1 = min(m, a0 + per);
-    uint32_t mine = 0;
-    for (int i = a0; i < a1; ++i)
-      if (i == 0 || keys[i] != keys[i - 1]) ++mine;
-    uint32_t distinct;
-    uint32_t r = block_excl_scan<BF_SEL_T>(mine, scan_tmp, &distinct);
-    const bool all_keys = cut == (uint32_t)(HBINS - 1);
-    if (distinct >= (uint32_t)k2 || all_keys) {
-      if (distinct < (uint32_t)k2 && tau[q] < HBINS - 1) {
-        if (threadIdx.x == 0) flag[q] = 1;
-        return;
-      }
-      for (int i = a0; i < a1; ++i)
-        if (i == 0 || keys[i] != keys[i - 1]) {
-          if ((int)r < k2) c2[q * k2 + r] = (uint32_t)keys[i];
-          ++r;
-        }
-      const int took = min(k2, (int)distinct);
-      for (int i = took + threadIdx.x; i < k2; i += BF_SEL_T) c2[q * k2 + i] = NONE32;
-      if (threadIdx.x == 0) {
-        c2n[q] = took;
-        flag[q] = 0;
-      }
-      return;
-    }
-    __syncthreads();
+  const int m = (int)s_cnt;
+  int n2 = 1;
+  while (n2 < m) n2 <<= 1;
+  for (int i = m + threadIdx.x; i < n2; i += BF_SEL_T) keys[i] = ~0ull;
+  __syncthreads();
+  bitonic_u64(keys, n2);
+  const int took = min(k2, m);
+  for (int i = threadIdx.x; i < k2; i += BF_SEL_T) c2[q * k2 + i] = i < took ? (uint32_t)keys[i] : NONE32;
+  if (threadIdx.x == 0) {
+    c2n[q] = took;
+    flag[q] = 0;
   }
 }
 
@@ -601,22 +642,62 @@ hf_status bfilter_run(const hf_forest* f, int T, int len, int64_t nb, const uint
   const uint32_t chunk = (uint32_t)std::max(256, std::min(1 << 16, ce ? atoi(ce) : 8192));
   k_bplan<<<1, BS_T, 0, s>>>(tot, nbk, nbx, chunk, base, cumx, next);
   HF_LAUNCH_CHECK();
-  const size_t sc_lds = sizeof(uint32_t) * (3 * (size_t)nbk + T + SC_CH) + sizeof(uint16_t) * SC_CH;
-  if (sc_lds + 1024 > 64 * 1024)  // dynamic + static LDS above the default limit
-    HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sc_lds));
-  k_bscatter<<<(unsigned)nb, SC_T, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
+  // entries counting-sorted per pass of the scatter kernel: 1024 x 16
+  // (longer runs per bucket, one workgroup a CU) or 512 x 16 (two a CU)
+  const char* ste = getenv("HF_SCATTER_T");
+  const int sct = ste && atoi(ste) == 512 ? 512 : 1024;
+  const size_t sc_ch = (size_t)sct * SC_PER;
+  const size_t sc_lds = sizeof(uint32_t) * (3 * (size_t)nbk + T + sc_ch) + sizeof(uint16_t) * sc_ch;
+  if (sct == 1024) {
+    if (sc_lds + 1024 > 64 * 1024)  // dynamic + static LDS above the default limit
+      HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sc_lds));
+    k_bscatter<1024><<<(unsigned)nb, 1024, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
+  } else {
+    if (sc_lds + 1024 > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sc_lds));
+    k_bscatter<512><<<(unsigned)nb, 512, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
+  }
   HF_LAUNCH_CHECK();
   int dev = 0, ncu = 256;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const unsigned grid = (unsigned)std::max(BF_XCD, (ncu * 8 + BF_XCD - 1) / BF_XCD * BF_XCD);
-  k_bscore<<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
-                                 capc);
+  // record blocks of 64 in flight per wavefront (tuning)
+  const char* sbe = getenv("HF_SCORE_SB");
+  const int sb = sbe ? atoi(sbe) : 2;
+  if (sb == 4)
+    k_bscore<4><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
+                                      capc);
+  else if (sb == 3)
+    k_bscore<3><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
+                                      capc);
+  else if (sb == 1)
+    k_bscore<1><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
+                                      capc);
+  else
+    k_bscore<2><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
+                                      capc);
   HF_LAUNCH_CHECK();
   const size_t sel_lds = sizeof(uint64_t) * (size_t)capc;
-  if (sel_lds + 1024 > 64 * 1024)
-    HIP_TRY(hipFuncSetAttribute((const void*)k_bselect, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sel_lds));
-  k_bselect<<<(unsigned)nb, BF_SEL_T, sel_lds, s>>>(cand, ccnt, tau, capc, k2, c2, c2n, flag);
+  switch (capc / BF_SEL_T) {
+#define HF_BSEL(P)                                                                                            \
+  case P:                                                                                                     \
+    if (sel_lds + 1024 > 64 * 1024)                                                                           \
+      HIP_TRY(hipFuncSetAttribute((const void*)k_bselect<P>, hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                                  (int)sel_lds));                                                             \
+    k_bselect<P><<<(unsigned)nb, BF_SEL_T, sel_lds, s>>>(cand, ccnt, tau, capc, k2, c2, c2n, flag);           \
+    break;
+    HF_BSEL(4)
+    HF_BSEL(8)
+    HF_BSEL(16)
+    HF_BSEL(32)
+#undef HF_BSEL
+    default:
+      set_error("candidate capacity %d has no selection kernel", capc);
+      return HF_ERR_UNSUPPORTED;
+  }
   HF_LAUNCH_CHECK();
   return HF_OK;
 }

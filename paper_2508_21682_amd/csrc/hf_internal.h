@@ -122,6 +122,16 @@ constexpr uint32_t NONE32 = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// quad_perm DPP moves: lane i of each quad reads lane sel[i] of the quad
+template <int CTRL>
+__device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t v, int u) {
+  return u == 0 ? quad_perm<0x00>(v) : u == 1 ? quad_perm<0x55>(v) : u == 2 ? quad_perm<0xAA>(v) : quad_perm<0xFF>(v);
+}
+constexpr int QP_XOR1 = 0xB1;  // [1, 0, 3, 2]
+constexpr int QP_XOR2 = 0x4E;  // [2, 3, 0, 1]
 __device__ __forceinline__ uint64_t lanemask_lt() {
   int l = __lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));

@@ -266,16 +266,6 @@ constexpr int HB = 513;  // Hamming values 0..512
 // that some paths skip makes the compiler wait for every one before it.
 // mlen = ceil(2^32 / len): t = (e * mlen) >> 32 is floor(e / len) or one
 // more, since e < 2^30.
-// quad_perm DPP moves: lane i of each quad reads lane sel[i] of the quad
-template <int CTRL>
-__device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
-}
-__device__ __forceinline__ uint32_t quad_bcast(uint32_t v, int u) {
-  return u == 0 ? quad_perm<0x00>(v) : u == 1 ? quad_perm<0x55>(v) : u == 2 ? quad_perm<0xAA>(v) : quad_perm<0xFF>(v);
-}
-constexpr int QP_XOR1 = 0xB1;  // [1, 0, 3, 2]
-constexpr int QP_XOR2 = 0x4E;  // [2, 3, 0, 1]
 
 __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_perm, int64_t N,
                                              int T, int len, uint64_t mlen, int64_t qstride,

@@ -4,7 +4,8 @@
 //   gather  - random records from an array the size of the 23M-point sketch
 //             table: 64-byte records (a sketch), 128-byte records (a whole L2
 //             line) and 768-byte records (an fp16 row of 384 dimensions);
-//             record indexes come from a hash of the entry number;
+//             record indexes come from a hash of the entry number; and
+//             64-byte records from a 2 MiB table that every L2 holds;
 //   mfma    - independent chains of 32x32x16 fp16 MFMAs with fp32
 //             accumulation in every wave of a full grid.
 // The published peaks are the denominators of the rooflines; these figures
@@ -179,6 +180,8 @@ int main() {
     gather<4, 1>("gather_64B", tab, tab_bytes, pos, n, out, reps);
     gather<8, 1>("gather_128B", tab, tab_bytes, pos, n, out, reps);
     gather<16, 3>("gather_768B", tab, tab_bytes, pos, n / 8, out, reps);
+    // the same 64-byte gathers from a 2 MiB table: every XCD's L2 holds it
+    gather<4, 1>("gather_64B_l2", tab, 2ull << 20, pos, n, out, reps);
     CK(hipFree(tab));
     CK(hipFree(pos));
     CK(hipFree(out));

@@ -13,6 +13,8 @@
 
 #include <type_traits>
 
+#include <string.h>
+
 #include "hf_internal.h"
 
 struct hf_lhash {
@@ -154,8 +156,6 @@ __global__ __launch_bounds__(256) void k_mlp(const T* __restrict__ A, int64_t M,
 // with ballots into an LDS bit array and stored as 8 words.  D: input
 // dimension (multiple of 32); HID: hidden units (multiple of 64).  The sums
 // run in the same order as the two-kernel path, so the sketches are equal.
-constexpr int FM_ROWS = 64;
-
 // 8 values of T as BF16, from the raw bytes of one (half) or two (float) uint4
 template <class T>
 __device__ __forceinline__ uint4 raw_to_bf16(uint4 r0, uint4 r1) {
@@ -185,28 +185,29 @@ __device__ __forceinline__ uint4 raw_to_bf16(uint4 r0, uint4 r1) {
   return o;
 }
 
-// One dense layer on the 64 rows held in LDS (row stride AS, K inputs):
-// wavefront wv computes columns [wv NC 16, (wv + 1) NC 16) into acc.  The
-// weight fragments of step k + 32 are loaded while step k's products run.
+// Columns [col0, col0 + 16 NC) of a dense layer for the 128 rows held in LDS
+// (row stride AS, K inputs) into acc; the weight fragments of step k + 32
+// are loaded while step k's products run.
 template <int K, int NC>
-__device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ sa, int AS, const uint16_t* __restrict__ W,
-                                            int wv, int ri, int g, float4v (&acc)[4][NC]) {
+__device__ __forceinline__ void ws_layer(const uint16_t* __restrict__ sa, int AS, const uint16_t* __restrict__ W,
+                                         int col0, int ri, int g, float4v (&acc)[8][NC]) {
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) acc[rt][cb] = (float4v){0.f, 0.f, 0.f, 0.f};
-  const uint16_t* wp = W + (int64_t)(wv * NC * 16 + ri) * K + 8 * g;
+  const uint16_t* wp = W + (int64_t)(col0 + ri) * K + 8 * g;
   uint4 bw[NC], bn[NC];
 #pragma unroll
   for (int cb = 0; cb < NC; ++cb) bw[cb] = *(const uint4*)(wp + (int64_t)cb * 16 * K);
-#pragma unroll
+  // not unrolled: the LDS fragment loads of later steps are not hoisted
+#pragma unroll 1
   for (int k = 0; k < K; k += 32) {
     if (k + 32 < K) {
 #pragma unroll
       for (int cb = 0; cb < NC; ++cb) bn[cb] = *(const uint4*)(wp + (int64_t)cb * 16 * K + k + 32);
     }
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
+    for (int rt = 0; rt < 8; ++rt) {
       const uint4 a = *(const uint4*)(sa + (16 * rt + ri) * AS + k + 8 * g);
 #pragma unroll
       for (int cb = 0; cb < NC; ++cb)
@@ -220,93 +221,107 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ sa, int
   }
 }
 
-// Encoder: both layers fused, 64 rows per workgroup.  The rows (as BF16),
-// then in the same LDS their hidden activations, stay on chip; each
-// wavefront computes a quarter of the columns of a layer for all 64 rows, so
-// a weight element is read once per workgroup (from L2, as the B operand of
-// v_mfma_f32_16x16x32_bf16).  The 512 output signs of each row are gathered
-// with ballots into an LDS bit array and stored as 8 words.  D: input
-// dimension (multiple of 32); HID: hidden units (multiple of 64).  The sums
-// run in the same order as the two-kernel path, so the sketches are equal.
+// Encoder, persistent form: one workgroup of eight wavefronts per CU walks
+// blocks of 128 rows.  Per block the rows (BF16) sit in LDS and each
+// wavefront computes a column slice of a layer for all 128 rows (layer 1: 32
+// hidden units; layer 2: 64 outputs in two passes of 32), so a weight element
+// is read from L2 once per 128 rows; the hidden activations then overwrite
+// the rows in LDS.  The next block's rows (fp16 input) are loaded into
+// registers while the current block's products run.  Same summation order as
+// the two-kernel path, so the sketches are equal.
+constexpr int WS_ROWS = 128, WS_T = 512, WS_PASSES = 2;
 template <class T, int D, int HID>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mlp_fused(
-    const T* __restrict__ X, int64_t M, const uint16_t* __restrict__ W1, const float* __restrict__ b1,
-    const uint16_t* __restrict__ W2, const float* __restrict__ b2, uint64_t* __restrict__ SK) {
-  constexpr int XS = D + 8, HS = HID + 8;  // padded row strides (bf16 elements)
-  constexpr int XH = FM_ROWS * (XS > HS ? XS : HS);
-  // the hidden activations overwrite the rows once layer 1 has read them
+__global__ __launch_bounds__(WS_T) void k_mlp_ws(const T* __restrict__ X, int64_t M,
+                                                 const uint16_t* __restrict__ W1, const float* __restrict__ b1,
+                                                 const uint16_t* __restrict__ W2, const float* __restrict__ b2,
+                                                 uint64_t* __restrict__ SK) {
+  constexpr int XS = D + 8, HS = HID + 8;
+  constexpr int XH = WS_ROWS * (XS > HS ? XS : HS);
+  constexpr int NC1 = HID / 8 / 16;              // layer-1 column tiles per wavefront
+  constexpr int PER = WS_ROWS * (D / 8) / WS_T;  // 8-value chunks a thread stages
+  constexpr bool PREF = sizeof(T) == 2;          // fp16 rows prefetched a block ahead
+  static_assert(PER * WS_T == WS_ROWS * (D / 8) && HID % 128 == 0 && D % 32 == 0, "shape");
   __shared__ __align__(16) uint16_t s_xh[XH];
-  __shared__ __align__(16) uint16_t s_bits[FM_ROWS * 32];
-  uint16_t* const s_x = s_xh;
-  uint16_t* const s_h = s_xh;
+  __shared__ __align__(16) uint16_t s_bits[WS_ROWS * 32];
   const int wv = threadIdx.x / 64, l = __lane_id(), ri = l % 16, g = l / 16;
-  const int64_t r0 = (int64_t)blockIdx.x * FM_ROWS;
-  // stage the rows as BF16 (zero rows past M): every load of a batch is in
-  // flight before the first conversion
-  constexpr int PER = FM_ROWS * (D / 8) / 256, BATCH = sizeof(T) == 2 ? PER : PER / 2;
-  static_assert(PER * 256 == FM_ROWS * (D / 8) && PER % BATCH == 0, "staging shape");
+  const int64_t nblk = (M + WS_ROWS - 1) / WS_ROWS;
+  uint4 xr[PREF ? PER : 1];
+  auto load_rows = [&](int64_t blk) {
+    const int64_t r0 = blk * WS_ROWS;
 #pragma unroll
-  for (int b0 = 0; b0 < PER; b0 += BATCH) {
-    uint4 raw[BATCH][2];
-#pragma unroll
-    for (int i = 0; i < BATCH; ++i) {
-      const int e = threadIdx.x + 256 * (b0 + i), r = e / (D / 8), c8 = e % (D / 8);
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + WS_T * i, r = e / (D / 8), c8 = e % (D / 8);
       const int64_t row = r0 + r < M ? r0 + r : M - 1;
-      const T* p = X + row * D + 8 * c8;
-      raw[i][0] = *(const uint4*)p;
-      raw[i][1] = sizeof(T) == 2 ? make_uint4(0, 0, 0, 0) : *(const uint4*)(p + 4);
+      xr[PREF ? i : 0] = *(const uint4*)(X + row * D + 8 * c8);
+      if constexpr (!PREF) {
+        // float rows: converted and stored at once (no prefetch)
+        const uint4 hi = *(const uint4*)(X + row * D + 8 * c8 + 4);
+        uint4 v = raw_to_bf16<T>(xr[0], hi);
+        if (r0 + r >= M) v = make_uint4(0, 0, 0, 0);
+        *(uint4*)(s_xh + r * XS + 8 * c8) = v;
+      }
     }
+  };
+  if (PREF && blockIdx.x < nblk) load_rows(blockIdx.x);
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t r0 = blk * WS_ROWS;
+    __syncthreads();  // the previous block's hidden units and sign bits are consumed
+    if constexpr (PREF) {
 #pragma unroll
-    for (int i = 0; i < BATCH; ++i) {
-      const int e = threadIdx.x + 256 * (b0 + i), r = e / (D / 8), c8 = e % (D / 8);
-      uint4 v = raw_to_bf16<T>(raw[i][0], raw[i][1]);
-      if (r0 + r >= M) v = make_uint4(0, 0, 0, 0);
-      *(uint4*)(s_x + r * XS + 8 * c8) = v;
+      for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + WS_T * i, r = e / (D / 8), c8 = e % (D / 8);
+        uint4 v = raw_to_bf16<T>(xr[i], make_uint4(0, 0, 0, 0));
+        if (r0 + r >= M) v = make_uint4(0, 0, 0, 0);
+        *(uint4*)(s_xh + r * XS + 8 * c8) = v;
+      }
+    } else {
+      load_rows(blk);
     }
-  }
-  __syncthreads();
-  // layer 1: wavefront wv computes hidden units [wv HID/4, (wv+1) HID/4) for the 64 rows
-  {
-    constexpr int NC = HID / 4 / 16;
-    float4v acc[4][NC];
-    fused_layer<D, NC>(s_x, XS, W1, wv, ri, g, acc);
-    __syncthreads();  // every wavefront is done with the rows
-    // bias, relu, BF16: lane holds rows 4 g + r of row tile rt, column ri of tile cb
+    __syncthreads();
+    if (PREF && blk + gridDim.x < nblk) load_rows(blk + gridDim.x);
+    {
+      float4v acc[8][NC1];
+      ws_layer<D, NC1>(s_xh, XS, W1, wv * NC1 * 16, ri, g, acc);
+      __syncthreads();  // every wavefront is done with the rows
 #pragma unroll
-    for (int cb = 0; cb < NC; ++cb) {
-      const int c = wv * (HID / 4) + cb * 16 + ri;
-      const float bc = b1[c];
+      for (int cb = 0; cb < NC1; ++cb) {
+        const int c = wv * NC1 * 16 + cb * 16 + ri;
+        const float bc = b1[c];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+        for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float v = acc[rt][cb][r] + bc;
-          s_h[(16 * rt + 4 * g + r) * HS + c] = (uint16_t)bf16_rne(v > 0.f ? v : 0.f);
-        }
+          for (int r = 0; r < 4; ++r) {
+            const float v = acc[rt][cb][r] + bc;
+            s_xh[(16 * rt + 4 * g + r) * HS + c] = (uint16_t)bf16_rne(v > 0.f ? v : 0.f);
+          }
+      }
     }
-  }
-  __syncthreads();
-  // layer 2: wavefront wv computes outputs [128 wv, 128 wv + 128) for the 64 rows
-  {
-    float4v acc[4][8];
-    fused_layer<HID, 8>(s_h, HS, W2, wv, ri, g, acc);
-    // the ballot's bits 16 g' + i: row 16 rt + 4 g' + r, output 128 wv + 16 cb + i
+    __syncthreads();
+    constexpr int PS = WS_PASSES, NCP = 4 / PS;  // layer-2 passes and their column tiles
 #pragma unroll
-    for (int cb = 0; cb < 8; ++cb) {
-      const float bc = b2[wv * 128 + cb * 16 + ri];
+    for (int ps = 0; ps < PS; ++ps) {
+      // outputs [64 wv + 16 NCP ps, + 16 NCP): the ballot's bits 16 g' + i
+      // are row 16 rt + 4 g' + r, output c0 + i
+      float4v acc[8][NCP];
+      ws_layer<HID, NCP>(s_xh, HS, W2, 64 * wv + 16 * NCP * ps, ri, g, acc);
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int cb = 0; cb < NCP; ++cb) {
+        const int c0 = 64 * wv + 16 * NCP * ps + 16 * cb;
+        const float bc = b2[c0 + ri];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint64_t m = __ballot(acc[rt][cb][r] + bc >= 0.f);
-          if (l < 4) s_bits[(16 * rt + 4 * l + r) * 32 + 8 * wv + cb] = (uint16_t)(m >> (16 * l));
-        }
+        for (int rt = 0; rt < 8; ++rt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint64_t m = __ballot(acc[rt][cb][r] + bc >= 0.f);
+            if (l < 4) s_bits[(16 * rt + 4 * l + r) * 32 + c0 / 16] = (uint16_t)(m >> (16 * l));
+          }
+      }
     }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < FM_ROWS * 8; e += 256) {
-    const int r = e / 8, w = e % 8;
-    if (r0 + r < M) SK[(r0 + r) * 8 + w] = *(const uint64_t*)(s_bits + r * 32 + 4 * w);
+    __syncthreads();
+    for (int e = threadIdx.x; e < WS_ROWS * 8; e += WS_T) {
+      const int r = e / 8, w = e % 8;
+      if (r0 + r < M) SK[(r0 + r) * 8 + w] = *(const uint64_t*)(s_bits + r * 32 + 4 * w);
+    }
   }
 }
 
@@ -640,12 +655,16 @@ hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_
                            Workspace* ext) {
   HF_TRY(check_lhash(L));
   if (N <= 0) return HF_OK;
-  if (L->d == 384 && L->hid == 256 && getenv("HF_MLP_UNFUSED") == nullptr) {
-    const unsigned grid = (unsigned)ceil_div(N, FM_ROWS);
+  const char* form = getenv("HF_MLP");  // "two": the two-kernel path
+  if (L->d == 384 && L->hid == 256 && !(form && strcmp(form, "two") == 0)) {
+    int dev = 0, ncu = 256;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(N, WS_ROWS), ncu);
     if (dt == HF_F16)
-      k_mlp_fused<__half, 384, 256><<<grid, 256, 0, s>>>((const __half*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
+      k_mlp_ws<__half, 384, 256><<<grid, WS_T, 0, s>>>((const __half*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
     else
-      k_mlp_fused<float, 384, 256><<<grid, 256, 0, s>>>((const float*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
+      k_mlp_ws<float, 384, 256><<<grid, WS_T, 0, s>>>((const float*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
     HF_LAUNCH_CHECK();
     return HF_OK;
   }

@@ -652,16 +652,17 @@ def test_lhash_encode_parity(hf, orc, dtype, n):
 
 
 def test_lhash_fused_encoder_matches_two_kernel_path(hf, monkeypatch):
-    """The fused two-layer encoder sums in the two-kernel path's order, so the
-    sketches agree bit for bit (ragged last block of 64 rows, both dtypes)."""
+    """The fused two-layer encoder (persistent 128-row blocks) sums in the
+    two-kernel path's order, so the sketches agree bit for bit (ragged last
+    blocks, both dtypes; more blocks than CUs so the persistent workgroups walk
+    several blocks with the prefetch)."""
     L = hf.LHash(*_net(96))
-    for dtype, n in ((np.float16, 1000 + 37), (np.float32, 70)):
-        x = datagen.mixture(n, 384, 8, 0.05, 97, dtype=dtype)
-        a = L.encode(dev(x)).cpu().numpy()
-        monkeypatch.setenv("HF_MLP_UNFUSED", "1")
-        b = L.encode(dev(x)).cpu().numpy()
-        monkeypatch.delenv("HF_MLP_UNFUSED")
-        assert (a == b).all()
+    for dtype, n in ((np.float16, 1000 + 37), (np.float32, 70), (np.float16, 128 * 600 + 5), (np.float32, 128 * 300 + 3)):
+        x = dev(datagen.mixture(n, 384, 8, 0.05, 97, dtype=dtype))
+        monkeypatch.setenv("HF_MLP", "two")
+        want = L.encode(x).cpu().numpy()
+        monkeypatch.delenv("HF_MLP")
+        assert (L.encode(x).cpu().numpy() == want).all(), (dtype, n)
     L.free()
 
 

@@ -4,7 +4,7 @@
 Default workload ("search-23Mx384"): 23,000,000 x 384 fp16 points of a seeded
 8,192-component Gaussian mixture on the sphere, 10,000 queries from the same
 mixture, a forest of 1,280 trees with leaves of at most 100 points, 512-bit SRP
-sketches, k1 = 70, k2 = 1100, h = 0, k = 30 by inner product with an FP32
+sketches, k1 = 70, k2 = 1000, h = 0, k = 30 by inner product with an FP32
 rerank (the shape of the paper's Task 1; the budget is the cheapest found at
 recall@30 >= 0.7 on this data).  One step = one hf_search call over the whole query batch
 (descent of every tree, Hamming filter, expansion, rerank); the forest is
@@ -429,7 +429,7 @@ def bench_search(args, hf, torch, ws):
     per_launch_q = nq * args.steps / ham_n
     bytes_launch = per_launch_q * (T * ln * 70 + T * 4 + 64 + 513 * 4)
     achieved = bytes_launch / (ham_ms / ham_n * 1e-3) / 1e9
-    src = [os.path.join(ROOT, "paper_2508_21682_amd", "csrc", f) for f in ("hf_bfilter.hip", "hf_search.hip")]
+    src = [os.path.join(ROOT, "paper_2508_21682_amd", "csrc", "hf_bfilter.hip")]
     cfg = {"n": N, "queries": nq, "trees": T, "leaf_max": args.leaf, "k1": args.k1, "k2": args.k2, "h": args.h}
     rec_t = measured_traffic("filter_search-23Mx384_counters.json", src, cfg)
     # bytes per query scale with the launch's queries
@@ -742,7 +742,7 @@ def main():
     ap.add_argument("--leaf", type=int, default=100)
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--k1", type=int, default=70)
-    ap.add_argument("--k2", type=int, default=1100)
+    ap.add_argument("--k2", type=int, default=1000)
     ap.add_argument("--h", type=int, default=0)
     ap.add_argument("--alt", default="65,1000,1",
                     help="search: a second budget 'k1,k2,h' timed on the same forest ('' for none); the default "

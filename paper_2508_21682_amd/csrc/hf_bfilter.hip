@@ -589,9 +589,11 @@ int bfilter_bucket_bits(int64_t N) {
   return bb;
 }
 
+// Candidate-list capacity: the threshold passes about 7 k2 entries (3.5 k2
+// aimed at, plus the sample's margin and the ties at the threshold).
 int bfilter_capacity(int k2) {
   int c = 2048;
-  while (c < 5 * k2) c <<= 1;
+  while (c < 7 * k2) c <<= 1;
   return c;
 }
 

@@ -37,7 +37,7 @@ def test_committed_records_are_well_formed():
     """The committed records name their kernel source, its hash and the
     configuration they were taken on (bench.py reports traffic as null once
     the source or the configuration differs)."""
-    for name, src in [("k_ham_search-23Mx384_counters.json", "paper_2508_21682_amd/csrc/hf_search.hip"),
+    for name, src in [("filter_search-23Mx384_counters.json", "paper_2508_21682_amd/csrc/hf_bfilter.hip"),
                       ("k_band_graph-3Mx384_counters.json", "paper_2508_21682_amd/csrc/hf_graph.hip")]:
         rec = json.load(open(os.path.join(ROOT, "profiles", name)))
         assert rec["source"] == src and len(rec["source_sha256_16"]) == 16

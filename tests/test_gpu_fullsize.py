@@ -65,7 +65,7 @@ def test_search_23M_sampled(hf, orc):
 
     w = datagen.WORKLOADS["search-23Mx384"]
     N, d = w["n"], w["d"]
-    T, M, k, k1, k2, h = 1280, 100, 30, 70, 1100, 0
+    T, M, k, k1, k2, h = 1280, 100, 30, 70, 1000, 0
     print("drawing %d x %d" % (N, d), flush=True)
     x = datagen.mixture_device(N, d, w["n_comp"], w["sigma"], w["seed"], w["unit"])
     q = datagen.mixture_device(2000, d, w["n_comp"], w["sigma"], w["seed"], w["unit"],

@@ -719,11 +719,12 @@ def test_lhash_gradients_with_hard_negatives(hf, orc):
 
 def test_lhash_training_and_gain_over_srp(hf, orc):
     """Training on (query, true 10-NN) pairs, batches of nearby queries along a
-    Hilbert order, lowers the training loss.  The Hamming recall of the
-    neighbours (training and held-out queries) and the gain over SRP sketches
-    are measured and reported, not asserted: on this mixture, whose
-    within-cluster structure is isotropic noise, the trained network does not
-    beat SRP, which therefore stays the sketch in use (fallback and judge)."""
+    Hilbert order, lowers the training loss.  On this mixture, whose
+    within-cluster structure is isotropic noise, the trained network is
+    predicted to stay below SRP in the Hamming recall of the neighbours
+    (random hyperplanes already capture what an MLP could, and contrastive
+    training pulls cluster mates together, flattening the ranking inside a
+    cluster), and the test asserts that sign: SRP stays the sketch in use."""
     import torch
 
     x, q = datagen.mixture(20000, 384, 32, 0.05, 98, dtype=np.float16, query_seed=99, nq=3000)
@@ -753,5 +754,5 @@ def test_lhash_training_and_gain_over_srp(hf, orc):
     print("loss per epoch", curve, "recall@100 of 10-NN: training queries %.3f -> %.3f, held-out %.3f -> %.3f,"
           " SRP held-out %.3f (gain %+.3f)" % (fit_before, fit_after, held_before, held_after, srp, held_after - srp))
     assert curve[-1] < 0.8 * curve[0]
-    assert 0.0 <= held_after <= 1.0 and 0.0 <= srp <= 1.0
+    assert held_after < srp
     L.free()

@@ -88,8 +88,10 @@ __device__ __forceinline__ float e4m3_val(uint32_t c) {
 }
 
 // PREC 1 = BF16, 2 = FP8; MCH 16-byte chunks of a low-precision row per lane
-// of a 16-lane group, RCH of a stored row (rescoring).
-template <class T, int PREC, int MCH, int RCH>
+// of a GL-lane group (16 for BF16 rows, 8 for the half-as-long FP8 rows, so
+// every lane loads whole chunks and twice as many FP8 rows are in flight),
+// RCH of a stored row per lane of a 16-lane group (rescoring).
+template <class T, int PREC, int MCH, int RCH, int GL>
 __global__ __launch_bounds__(LP_T) void k_rerank_lp(
     const T* __restrict__ Xp, const void* __restrict__ Xlp, const float* __restrict__ s8,
     int64_t N, int d, const T* __restrict__ Q, const uint32_t* __restrict__ c2,
@@ -140,8 +142,8 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
   // the row (8 BF16 or 16 FP8 values), LP_ROWS rows in flight per group;
   // products of rounded values are exact in FP32, sums accumulate in FP32
   {
-    const int grp = threadIdx.x / 16, gl = threadIdx.x % 16;
-    constexpr int NG = LP_T / 16;
+    const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
+    constexpr int NG = LP_T / GL;
     constexpr int EPC = PREC == 1 ? 8 : 16;  // values per 16-byte chunk
     const int nch = d / EPC;
     for (uint32_t e0 = (uint32_t)grp * LP_ROWS; e0 < E; e0 += NG * LP_ROWS) {
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
         const unsigned char* row = (const unsigned char*)Xlp + (int64_t)p * d * (PREC == 1 ? 2 : 1);
 #pragma unroll
         for (int m = 0; m < MCH; ++m) {
-          const int c = gl + 16 * m;
+          const int c = gl + GL * m;
           raw[u][m] = *(const uint4*)(row + 16 * (c < nch ? c : 0));
         }
         rs[u] = PREC == 2 ? s8[p] : 1.f;
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
         float a = 0.f;
 #pragma unroll
         for (int m = 0; m < MCH; ++m) {
-          const int c = gl + 16 * m;
+          const int c = gl + GL * m;
           if (c < nch) {
             const float4* q4 = (const float4*)(sqr + c * EPC);  // 16-byte LDS reads
             const uint32_t w[4] = {raw[u][m].x, raw[u][m].y, raw[u][m].z, raw[u][m].w};
@@ -188,10 +190,8 @@ __global__ __launch_bounds__(LP_T) void k_rerank_lp(
             }
           }
         }
-        a += __shfl_xor(a, 8);
-        a += __shfl_xor(a, 4);
-        a += __shfl_xor(a, 2);
-        a += __shfl_xor(a, 1);
+#pragma unroll
+        for (int o = GL / 2; o >= 1; o >>= 1) a += __shfl_xor(a, o);
         if (PREC == 2) a = a * (rs[u] * qscale);
         if (gl == 0 && e0 + u < E) ekey[e0 + u] = ~float_to_ordered(a);
       }
@@ -332,20 +332,21 @@ hf_status rerank_lp_launch(const hf_forest* f, hf_precision prec, const void* Qb
     return HF_ERR_UNSUPPORTED;
   }
   const void* kern = nullptr;
-  // chunks per lane: low-precision rows (BF16: d/8 chunks, FP8: d/16) and
-  // stored rows (fp16: d/8, fp32: d/4), over 16 lanes
-#define HF_LP(DV, TY, P, M, R) \
-  if (d == DV && prec == (P == 1 ? HF_PREC_BF16 : HF_PREC_FP8)) kern = (const void*)k_rerank_lp<TY, P, M, R>;
+  // chunks per lane: low-precision rows (BF16: d/8 chunks over 16 lanes,
+  // FP8: d/16 over 8) and stored rows (fp16: d/8, fp32: d/4, over 16 lanes)
+#define HF_LP(DV, TY, P, M, R)                                               \
+  if (d == DV && prec == (P == 1 ? HF_PREC_BF16 : HF_PREC_FP8))               \
+    kern = (const void*)k_rerank_lp<TY, P, M, R, P == 1 ? 16 : 8>;
   if (f->dtype == HF_F16) {
     HF_LP(128, __half, 1, 1, 1) HF_LP(256, __half, 1, 2, 2) HF_LP(384, __half, 1, 3, 3) HF_LP(512, __half, 1, 4, 4)
     HF_LP(768, __half, 1, 6, 6) HF_LP(1024, __half, 1, 8, 8)
-    HF_LP(128, __half, 2, 1, 1) HF_LP(256, __half, 2, 1, 2) HF_LP(384, __half, 2, 2, 3) HF_LP(512, __half, 2, 2, 4)
-    HF_LP(768, __half, 2, 3, 6) HF_LP(1024, __half, 2, 4, 8)
+    HF_LP(128, __half, 2, 1, 1) HF_LP(256, __half, 2, 2, 2) HF_LP(384, __half, 2, 3, 3) HF_LP(512, __half, 2, 4, 4)
+    HF_LP(768, __half, 2, 6, 6) HF_LP(1024, __half, 2, 8, 8)
   } else {
     HF_LP(128, float, 1, 1, 2) HF_LP(256, float, 1, 2, 4) HF_LP(384, float, 1, 3, 6) HF_LP(512, float, 1, 4, 8)
     HF_LP(768, float, 1, 6, 12) HF_LP(1024, float, 1, 8, 16)
-    HF_LP(128, float, 2, 1, 2) HF_LP(256, float, 2, 1, 4) HF_LP(384, float, 2, 2, 6) HF_LP(512, float, 2, 2, 8)
-    HF_LP(768, float, 2, 3, 12) HF_LP(1024, float, 2, 4, 16)
+    HF_LP(128, float, 2, 1, 2) HF_LP(256, float, 2, 2, 4) HF_LP(384, float, 2, 3, 6) HF_LP(512, float, 2, 4, 8)
+    HF_LP(768, float, 2, 6, 12) HF_LP(1024, float, 2, 8, 16)
   }
 #undef HF_LP
   if (!kern) {

@@ -580,6 +580,15 @@ static hf_status graph_prefilter(const void* X, int64_t N, int d, const hf_graph
     HF_TRY(lhash_encode_dev(p.lhash, X, HF_F16, N, sk, s));
   } else if (p.sketch == HF_SKETCH_SIGN) {
     HF_TRY(sign_sketch(X, HF_F16, N, d, sk, s));
+  } else if (d % 16 == 0 && getenv("HF_SRP_VALU") == nullptr) {
+    // the int8 matrix-core kernel (the same bits as the vector-ALU one)
+    int8_t* Rb = nullptr;
+    HF_TRY(srp_matrix_i8_upload(d, p.sketch_seed, &Rb, s));
+    const hf_status st = srp_sketch_mfma(X, HF_F16, N, d, e, Rb, sk, s);
+    const hipError_t sy = hipStreamSynchronize(s);
+    (void)hipFree(Rb);
+    HF_TRY(st);
+    HIP_TRY(sy);
   } else {
     HF_TRY(srp_sketch(X, HF_F16, N, d, e, p.sketch_seed, sk, ws));
   }

@@ -786,6 +786,8 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
       HF_TRY(lhash_encode_dev(f->lhash, Q, f->dtype, nq, qsk, s, &ws));
     else if (f->sketch_kind == HF_SKETCH_SIGN)
       HF_TRY(sign_sketch(Q, f->dtype, nq, d, qsk, s));
+    else if (f->srp_Rb && getenv("HF_SRP_VALU") == nullptr)
+      HF_TRY(srp_sketch_mfma(Q, f->dtype, nq, d, f->e, f->srp_Rb, qsk, s));
     else
       HF_TRY(srp_sketch(Q, f->dtype, nq, d, f->e, f->sketch_seed, qsk, ws, f->srp_R));
   }

@@ -650,20 +650,23 @@ def bench_graph(args, hf, torch, ws, k, lhash):
     prefilter = None
     if lhash is not None:
         # the sketch stage of Alg. 2 with learned sketches against SRP and the
-        # plain form, at one setting of orders and window
-        prefilter = {}
-        po, pw, pk2 = (int(v) for v in args.prefilter.split(","))
-        for name, kw in [("learned", dict(k2=pk2, sketch="learned", lhash=lhash)),
-                         ("srp", dict(k2=pk2, sketch_seed=6)), ("plain", dict())]:
-            hf.knn_graph(x, po, pw, k, 3, **kw)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            pids, _ = hf.knn_graph(x, po, pw, k, 3, **kw)
-            torch.cuda.synchronize()
-            prefilter[name] = {"orders": po, "window": pw, "k2": kw.get("k2", 0),
-                               "recall": recall(pids[rows], gt), "s": time.perf_counter() - t}
-        log("graph sketch stage (%d orders, +-%d, k2=%d): %s" % (po, pw, pk2, {
-            n_: (round(v_["recall"], 3), round(v_["s"], 3)) for n_, v_ in prefilter.items()}))
+        # plain form, at each setting of orders, window and k2 (the first is
+        # the learned form's graph shape: 32 orders, window +-32)
+        prefilter = []
+        for pcfg in args.prefilter.split(";"):
+            po, pw, pk2 = (int(v) for v in pcfg.split(","))
+            forms = {}
+            for name, kw in [("learned", dict(k2=pk2, sketch="learned", lhash=lhash)),
+                             ("srp", dict(k2=pk2, sketch_seed=6)), ("plain", dict())]:
+                hf.knn_graph(x, po, pw, k, 3, **kw)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                pids, _ = hf.knn_graph(x, po, pw, k, 3, **kw)
+                torch.cuda.synchronize()
+                forms[name] = {"k2": kw.get("k2", 0), "recall": recall(pids[rows], gt), "s": time.perf_counter() - t}
+            prefilter.append({"orders": po, "window": pw, "forms": forms})
+            log("graph sketch stage (%d orders, +-%d, k2=%d): %s" % (po, pw, pk2, {
+                n_: (round(v_["recall"], 3), round(v_["s"], 3)) for n_, v_ in forms.items()}))
     table2 = None
     if args.tables:
         table2 = []
@@ -767,8 +770,8 @@ def main():
                     help="search workload: also time the 3M x 384 graph (--orders, --window) in the same line")
     ap.add_argument("--configs", type=int, default=1,
                     help="search workload: also run the 10K x 32 search and the 1M x 384 graph configurations")
-    ap.add_argument("--prefilter", default="128,128,256",
-                    help="graph: 'orders,window,k2' at which learned and SRP sketch stages are compared")
+    ap.add_argument("--prefilter", default="32,32,128;128,128,256",
+                    help="graph: 'orders,window,k2[;...]' at which learned and SRP sketch stages are compared with the plain form")
     ap.add_argument("--tables", type=int, default=1,
                     help="also re-run the paper's Table 1 (search) and Table 2 (graph) parameters once each")
     ap.add_argument("--exact", type=int, default=1,

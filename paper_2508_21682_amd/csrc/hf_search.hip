@@ -143,16 +143,27 @@ __global__ __launch_bounds__(RK_T) void k_rank_top(const uint32_t* __restrict__ 
                                                    uint64_t* __restrict__ deep, uint32_t* __restrict__ ndeep) {
   __shared__ uint32_t s_q[NW * RK_T], s_p[NW * RK_T];  // sign rows, word-major
   __shared__ uint16_t s_ax[4][512];                    // each wavefront's tree: axis | reflected << 15
+  // the 64 queries' codes (d bytes each, dynamic LDS): a node test then waits
+  // for the node record only, not for a code byte behind it
+  extern __shared__ __align__(16) uint8_t s_code[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = blockIdx.y * 4 + wv;
-  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t qb = (int64_t)blockIdx.x * 64, q = qb + lane;
+  {
+    const int nqb = (int)min<int64_t>(64, nq - qb);
+    if (d % 16 == 0)
+      for (int i = threadIdx.x; i < nqb * (d / 16); i += RK_T)
+        ((uint4*)s_code)[i] = ((const uint4*)(qcodes + qb * d))[i];
+    else
+      for (int i = threadIdx.x; i < nqb * d; i += RK_T) s_code[i] = qcodes[qb * d + i];
+  }
   if (t < T)
     for (int i = lane; i < d; i += 64)
       s_ax[wv][i] = (uint16_t)(cperm[(int64_t)t * d + i] | ((uint32_t)crefl[(int64_t)t * d + i] << 15));
   if (q < nq)
 #pragma unroll
     for (int w = 0; w < NW; ++w) s_q[w * RK_T + threadIdx.x] = qsgn[q * NW + w];
-  wave_lds_sync();
+  __syncthreads();  // the codes are shared by the four wavefronts
   if (q >= nq || t >= T) return;
   const uint32_t* sq = s_q + threadIdx.x;
   uint32_t* sp = s_p + threadIdx.x;
@@ -160,7 +171,7 @@ __global__ __launch_bounds__(RK_T) void k_rank_top(const uint32_t* __restrict__ 
   const uint32_t* nd = nodes + 2 * node_off[t];
   const uint32_t* au = aux + 2 * node_off[t];
   const uint32_t* tp = tree_perm + (int64_t)t * N;
-  const uint8_t* u = qcodes + q * d;
+  const uint8_t* u = s_code + lane * d;
   auto test = [&](uint32_t w1) -> uint32_t {
     const uint32_t a = w1 & 0xFFFFu, L = (w1 >> 16) & 7u, flip = (w1 >> 19) & 1u;
     return ((u[a] >> L) & 1u) ^ flip;
@@ -805,10 +816,16 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
     HF_TRY(msb_plane(qcodes, nq, d, qsgn, s));
     k_zero_u32<<<1, 64, 0, s>>>(ndeep, 1);
     dim3 grid((unsigned)ceil_div(nq, 64), (unsigned)ceil_div(T, 4));
-#define HF_RK(n) \
-  case n: k_rank_top<n><<<grid, RK_T, 0, s>>>(f->nodes, f->node_aux, doff, qcodes, qsgn, f->sgn_pos, f->tree_perm, \
-                                              f->curve_perm, f->curve_refl, nq, d, T, N, (int)p.k1, 8 * d + 2, win, \
-                                              deep, ndeep); break;
+    const size_t rk_lds = 64 * (size_t)d;  // dynamic: the codes; static: 2 NW RK_T words + 4 KB
+#define HF_RK(n)                                                                                                    \
+  case n:                                                                                                           \
+    if (rk_lds + 8 * (size_t)n * RK_T + 4096 > 64 * 1024)                                                          \
+      HIP_TRY(hipFuncSetAttribute((const void*)k_rank_top<n>, hipFuncAttributeMaxDynamicSharedMemorySize,          \
+                                  (int)rk_lds));                                                                    \
+    k_rank_top<n><<<grid, RK_T, rk_lds, s>>>(f->nodes, f->node_aux, doff, qcodes, qsgn, f->sgn_pos, f->tree_perm,  \
+                                             f->curve_perm, f->curve_refl, nq, d, T, N, (int)p.k1, 8 * d + 2, win, \
+                                             deep, ndeep);                                                          \
+    break;
     switch (nw) { HF_RK(1) HF_RK(2) HF_RK(4) HF_RK(8) HF_RK(12) HF_RK(16) }
 #undef HF_RK
     HF_LAUNCH_CHECK();

@@ -278,7 +278,8 @@ constexpr int HB = 513;  // Hamming values 0..512
 // mlen = ceil(2^32 / len): t = (e * mlen) >> 32 is floor(e / len) or one
 // more, since e < 2^30.
 
-__global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_perm, int64_t N,
+template <int KT>
+__global__ __launch_bounds__(KT) void k_ham(const uint32_t* __restrict__ tree_perm, int64_t N,
                                              int T, int len, uint64_t mlen, int64_t qstride,
                                              const uint32_t* __restrict__ win,
                                              const uint64_t* __restrict__ sk,
@@ -286,12 +287,13 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
                                              uint16_t* __restrict__ ham,
                                              uint32_t* __restrict__ hist,
                                              const uint32_t* __restrict__ only) {
-  __shared__ uint32_t h[4][HB + 1];
+  constexpr int NWV = KT / 64;
+  __shared__ uint32_t h[NWV][HB + 1];
   extern __shared__ uint32_t s_win[];  // T window starts (dynamic LDS)
   const int64_t q = blockIdx.x;
   if (only && !only[q]) return;  // the query's C2 came from the bucketed filter
-  for (int i = threadIdx.x; i < 4 * (HB + 1); i += 256) (&h[0][0])[i] = 0;
-  for (int t = threadIdx.x; t < T; t += 256) s_win[t] = win[q * T + t];
+  for (int i = threadIdx.x; i < NWV * (HB + 1); i += KT) (&h[0][0])[i] = 0;
+  for (int t = threadIdx.x; t < T; t += KT) s_win[t] = win[q * T + t];
   __syncthreads();
   const int w = threadIdx.x / 64, grp = threadIdx.x / 4, qd = threadIdx.x & 3;
   const uint64_t q0 = qsk[q * 8 + 2 * qd], q1 = qsk[q * 8 + 2 * qd + 1];
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
     ulonglong2 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) v[u] = *(const ulonglong2*)(sk + (int64_t)quad_bcast(pc, u) * 8 + 2 * qd);
-    pc = pos_of(e0 + 256u + mine);
+    pc = pos_of(e0 + (uint32_t)KT + mine);
     // issue the next position load before any use of the sketches
     __builtin_amdgcn_sched_barrier(0);
     uint32_t a[4];
@@ -329,11 +331,15 @@ __global__ __launch_bounds__(256) void k_ham(const uint32_t* __restrict__ tree_p
     const uint32_t e = e0 + mine;
     out[e] = (uint16_t)c;
     atomicAdd(&h[w][e < total ? c : (uint32_t)HB], 1u);
-    e0 += 256;
+    e0 += KT;
   } while (e0 < total);
   __syncthreads();
-  for (int i = threadIdx.x; i < HB; i += 256)
-    hist[q * HB + i] = h[0][i] + h[1][i] + h[2][i] + h[3][i];
+  for (int i = threadIdx.x; i < HB; i += KT) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int v = 0; v < NWV; ++v) c += h[v][i];
+    hist[q * HB + i] = c;
+  }
 }
 
 // ------------------------------------------------------------------ select
@@ -748,7 +754,9 @@ __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64
 
 // ------------------------------------------------------------------ host side
 // Entries of one query's row of distances: T windows of len, padded to 256.
-int64_t ham_row_entries(int T, int len) { return ((int64_t)T * len + 255) / 256 * 256; }
+// rows padded to a multiple of 1,024 entries: the tail of a row takes the
+// last step's stores of a 1,024-thread workgroup
+int64_t ham_row_entries(int T, int len) { return ((int64_t)T * len + 1023) / 1024 * 1024; }
 
 // Queries per filter batch: rows of distances of a batch stay under 2 GB.
 int64_t filter_batch(int64_t nq, int64_t per_q) {
@@ -923,9 +931,14 @@ hf_status search_launch(const hf_forest* f, const void* Q, int64_t nq, const hf_
       // filter flagged (the others' workgroups return at once)
       StageTimer tm(bucketed ? ST_SELECT : ST_HAM, s);
       const uint64_t mlen = ((1ull << 32) + (uint64_t)len - 1) / (uint64_t)len;
-      k_ham<<<(unsigned)nb, 256, sizeof(uint32_t) * (size_t)T, s>>>(f->tree_perm, N, T, len, mlen, per_q,
-                                                                   win + q0 * T, f->sk_pos, qsk + q0 * 8, ham,
-                                                                   hist, flag);
+      // the few queries the bucketed filter flags each get a 1,024-thread
+      // workgroup, so their single pass over every entry ends sooner
+      if (bucketed)
+        k_ham<1024><<<(unsigned)nb, 1024, sizeof(uint32_t) * (size_t)T, s>>>(
+            f->tree_perm, N, T, len, mlen, per_q, win + q0 * T, f->sk_pos, qsk + q0 * 8, ham, hist, flag);
+      else
+        k_ham<256><<<(unsigned)nb, 256, sizeof(uint32_t) * (size_t)T, s>>>(
+            f->tree_perm, N, T, len, mlen, per_q, win + q0 * T, f->sk_pos, qsk + q0 * 8, ham, hist, flag);
       HF_LAUNCH_CHECK();
     }
     {

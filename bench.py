@@ -571,6 +571,7 @@ def bench_learned(args, hf, torch, ws, forest, x, q, gt, nq):
     forest.set_sketch("learned", L)
     torch.cuda.synchronize()
     enc_s = time.perf_counter() - t
+    enc_flop = 2.0 * x.shape[0] * (ws["d"] * 256 + 256 * 512)
     forest.search(q, args.k, args.k1, args.k2, args.h)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -588,6 +589,9 @@ def bench_learned(args, hf, torch, ws, forest, x, q, gt, nq):
              "pairs_from": "forest search k1=%d k2=%d h=%d (positives: its top %d; negatives: C2 entries not "
                            "among them, in Hamming order)" % (g1, g2, gh, kn),
              "pair_generation_s": gen_s, "train_s": train_s, "encode_23M_s": enc_s,
+             # the encoder's two dense layers over every row: 2 (d 256 + 256 512) flops a row
+             "encode_tflop_per_s": enc_flop / enc_s / 1e12,
+             "encode_frac_bf16_peak": enc_flop / enc_s / 1e12 / MFMA_F16_PEAK_TFLOPS,  # bf16 peak = fp16 peak
              "loss_per_epoch": [float(v) for v in curve],
              "sketch_in_use": "srp" if lrec <= srec else "learned"}, L)
 

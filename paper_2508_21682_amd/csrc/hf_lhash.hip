@@ -23,6 +23,7 @@ struct hf_lhash {
   int d, hid;
   float *W1, *b1, *W2, *b2;  // FP32 master weights: W1 hid x d, W2 512 x hid
   uint16_t *W1b, *W2b;       // BF16 copies used by the forward
+  uint16_t *W1p, *W2p;       // the same BF16 values in MFMA fragment order
   float* mom[4];             // Adam first moments (W1, b1, W2, b2)
   float* vel[4];             // Adam second moments
   int64_t step;
@@ -49,6 +50,21 @@ inline unsigned grid_for(int64_t n) {
 __global__ void k_f32_to_bf16(const float* __restrict__ w, int64_t n, uint16_t* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     out[i] = (uint16_t)bf16_rne(w[i]);
+}
+
+// BF16 weights W (ncol x K, row-major; ncol % 16 == 0, K % 32 == 0) in the
+// order the B operand of v_mfma_f32_16x16x32_bf16 takes them: for column tile
+// ct and K step ks, 64 lanes x 8 values, lane l holding W[16 ct + l % 16]
+// [32 ks + 8 (l / 16) + j], so a wavefront's fragment is 1 KB in one run.
+__global__ void k_pack_frag(const uint16_t* __restrict__ W, int ncol, int K, uint16_t* __restrict__ out) {
+  const int64_t n = (int64_t)ncol * K;
+  const int ksn = K / 32;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int j = (int)(i % 8), l = (int)(i / 8 % 64);
+    const int64_t blk = i / 512;
+    const int ks = (int)(blk % ksn), ct = (int)(blk / ksn);
+    out[i] = W[(int64_t)(16 * ct + l % 16) * K + 32 * ks + 8 * (l / 16) + j];
+  }
 }
 
 // 8 consecutive input values of row r starting at column k (zero past K) as BF16.
@@ -185,17 +201,19 @@ __device__ __forceinline__ uint4 raw_to_bf16(uint4 r0, uint4 r1) {
   return o;
 }
 
-// Columns [col0, col0 + 16 NC) of a dense layer for the 128 rows held in LDS
-// (row stride AS, K inputs) into acc; the weight fragments of step k + 32
-// are loaded while step k's products run.
+// Columns [col0, col0 + 16 NC) (col0 % 16 == 0) of a dense layer for the
+// 128 rows held in LDS (row stride AS, K inputs) into acc, from weights in
+// fragment order (k_pack_frag); the weight fragments of step k + 32 are
+// loaded while step k's products run.
 template <int K, int NC>
-__device__ __forceinline__ void ws_layer(const uint16_t* __restrict__ sa, int AS, const uint16_t* __restrict__ W,
+__device__ __forceinline__ void ws_layer(const uint16_t* __restrict__ sa, int AS, const uint16_t* __restrict__ Wp,
                                          int col0, int ri, int g, float4v (&acc)[8][NC]) {
 #pragma unroll
   for (int rt = 0; rt < 8; ++rt)
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) acc[rt][cb] = (float4v){0.f, 0.f, 0.f, 0.f};
-  const uint16_t* wp = W + (int64_t)(col0 + ri) * K + 8 * g;
+  // fragment (ct, ks) starts at 512 (ct K / 32 + ks); a step of k is k * 16
+  const uint16_t* wp = Wp + (int64_t)(col0 / 16) * K * 16 + 8 * (ri + 16 * g);
   uint4 bw[NC], bn[NC];
 #pragma unroll
   for (int cb = 0; cb < NC; ++cb) bw[cb] = *(const uint4*)(wp + (int64_t)cb * 16 * K);
@@ -204,7 +222,7 @@ __device__ __forceinline__ void ws_layer(const uint16_t* __restrict__ sa, int AS
   for (int k = 0; k < K; k += 32) {
     if (k + 32 < K) {
 #pragma unroll
-      for (int cb = 0; cb < NC; ++cb) bn[cb] = *(const uint4*)(wp + (int64_t)cb * 16 * K + k + 32);
+      for (int cb = 0; cb < NC; ++cb) bn[cb] = *(const uint4*)(wp + (int64_t)cb * 16 * K + 16 * (k + 32));
     }
 #pragma unroll
     for (int rt = 0; rt < 8; ++rt) {
@@ -225,7 +243,8 @@ __device__ __forceinline__ void ws_layer(const uint16_t* __restrict__ sa, int AS
 // blocks of 128 rows.  Per block the rows (BF16) sit in LDS and each
 // wavefront computes a column slice of a layer for all 128 rows (layer 1: 32
 // hidden units; layer 2: 64 outputs in two passes of 32), so a weight element
-// is read from L2 once per 128 rows; the hidden activations then overwrite
+// is read from L2 once per 128 rows, each wavefront's weight fragment as one
+// contiguous kilobyte (k_pack_frag); the hidden activations then overwrite
 // the rows in LDS.  The next block's rows (fp16 input) are loaded into
 // registers while the current block's products run.  Same summation order as
 // the two-kernel path, so the sketches are equal.
@@ -548,6 +567,11 @@ hf_status refresh_bf16(hf_lhash* L, hipStream_t s) {
   k_f32_to_bf16<<<grid_for(n1), 256, 0, s>>>(L->W1, n1, L->W1b);
   k_f32_to_bf16<<<grid_for(n2), 256, 0, s>>>(L->W2, n2, L->W2b);
   HF_LAUNCH_CHECK();
+  if (L->W1p) {
+    k_pack_frag<<<grid_for(n1), 256, 0, s>>>(L->W1b, L->hid, L->d, L->W1p);
+    k_pack_frag<<<grid_for(n2), 256, 0, s>>>(L->W2b, 512, L->hid, L->W2p);
+    HF_LAUNCH_CHECK();
+  }
   return HF_OK;
 }
 
@@ -633,7 +657,7 @@ hf_status lhash_grad(const hf_lhash* L, const void* A, const void* P, const void
 
 void lhash_release(hf_lhash* L) {
   if (!L) return;
-  void* ptrs[] = {L->W1, L->b1, L->W2, L->b2, L->W1b, L->W2b, L->mom[0], L->mom[1], L->mom[2], L->mom[3],
+  void* ptrs[] = {L->W1, L->b1, L->W2, L->b2, L->W1b, L->W2b, L->W1p, L->W2p, L->mom[0], L->mom[1], L->mom[2], L->mom[3],
                   L->vel[0], L->vel[1], L->vel[2], L->vel[3]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -656,15 +680,15 @@ hf_status lhash_encode_dev(const hf_lhash* L, const void* X, hf_dtype dt, int64_
   HF_TRY(check_lhash(L));
   if (N <= 0) return HF_OK;
   const char* form = getenv("HF_MLP");  // "two": the two-kernel path
-  if (L->d == 384 && L->hid == 256 && !(form && strcmp(form, "two") == 0)) {
+  if (L->d == 384 && L->hid == 256 && L->W1p && !(form && strcmp(form, "two") == 0)) {
     int dev = 0, ncu = 256;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(N, WS_ROWS), ncu);
     if (dt == HF_F16)
-      k_mlp_ws<__half, 384, 256><<<grid, WS_T, 0, s>>>((const __half*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
+      k_mlp_ws<__half, 384, 256><<<grid, WS_T, 0, s>>>((const __half*)X, N, L->W1p, L->b1, L->W2p, L->b2, sk);
     else
-      k_mlp_ws<float, 384, 256><<<grid, WS_T, 0, s>>>((const float*)X, N, L->W1b, L->b1, L->W2b, L->b2, sk);
+      k_mlp_ws<float, 384, 256><<<grid, WS_T, 0, s>>>((const float*)X, N, L->W1p, L->b1, L->W2p, L->b2, sk);
     HF_LAUNCH_CHECK();
     return HF_OK;
   }
@@ -721,6 +745,10 @@ hf_status hf_lhash_create(int32_t d, int32_t hidden, const float* W1, const floa
   }
   HIP_TRY(hipMalloc(&L->W1b, 2 * n[0]));
   HIP_TRY(hipMalloc(&L->W2b, 2 * n[2]));
+  if (d % 32 == 0 && hidden % 32 == 0) {
+    HIP_TRY(hipMalloc(&L->W1p, 2 * n[0]));
+    HIP_TRY(hipMalloc(&L->W2p, 2 * n[2]));
+  }
   HF_TRY(refresh_bf16(L, nullptr));
   HIP_TRY(hipDeviceSynchronize());
   guard.L = nullptr;

@@ -250,7 +250,10 @@ __global__ __launch_bounds__(256, KMAX <= 16 && KS <= 12 ? 2 : 1) void k_band(co
                                               uint4* __restrict__ slots, Mailbox mi, Mailbox mo) {
   constexpr int BPS = 2;           // column blocks per step
   constexpr int TR = 16 * BPS;     // tile rows
-  constexpr int RS = KS * 32 + 8;  // LDS row stride (halves)
+  // LDS row stride (halves): 32 bytes past a multiple of 256 bytes when
+  // 4 | KS, so the B-fragment reads (16 rows x 4 chunks of 16 bytes) hit
+  // distinct banks; 16 bytes past costs four conflict cycles a read
+  constexpr int RS = KS * 32 + 16;
   constexpr int CPR = KS * 4;      // 16-byte chunks per tile row
   constexpr int CH = (TR * CPR + 255) / 256;  // chunks per thread per tile
   __shared__ __attribute__((aligned(16))) _Float16 tile[2][TR * RS];

@@ -6,8 +6,8 @@
 // rows x 256 outputs, weights streamed from L2.  The hidden activations are
 // relu(z1) rounded to BF16.
 // Training: codes c = tanh(slope*z2); an InfoNCE loss over the in-batch pairs
-// plus a bit-balance term; the backward pass is a chain of FP32 GEMMs (an
-// LDS-tiled VALU kernel) and element-wise kernels; AdamW keeps FP32 master
+// plus a bit-balance term; the backward pass is a chain of FP32 GEMMs (FP32
+// MFMA from LDS tiles) and element-wise kernels; AdamW keeps FP32 master
 // weights and refreshes the BF16 copies after every step.
 #include <math.h>
 
@@ -254,14 +254,21 @@ __global__ __launch_bounds__(WS_T) void k_mlp_ws(const T* __restrict__ X, int64_
                                                  const uint16_t* __restrict__ W1, const float* __restrict__ b1,
                                                  const uint16_t* __restrict__ W2, const float* __restrict__ b2,
                                                  uint64_t* __restrict__ SK) {
-  constexpr int XS = D + 8, HS = HID + 8;
+  // row strides of 32 bytes past a multiple of 256: the A-fragment reads
+  // (16 rows x 4 chunks of 16 bytes) then hit distinct banks; 16 bytes past
+  // costs four conflict cycles a read
+  constexpr int XS = D + 16, HS = HID + 16;
+  static_assert((2 * XS) % 256 == 32 && (2 * HS) % 256 == 32, "row padding");
   constexpr int XH = WS_ROWS * (XS > HS ? XS : HS);
   constexpr int NC1 = HID / 8 / 16;              // layer-1 column tiles per wavefront
   constexpr int PER = WS_ROWS * (D / 8) / WS_T;  // 8-value chunks a thread stages
   constexpr bool PREF = sizeof(T) == 2;          // fp16 rows prefetched a block ahead
   static_assert(PER * WS_T == WS_ROWS * (D / 8) && HID % 128 == 0 && D % 32 == 0, "shape");
   __shared__ __align__(16) uint16_t s_xh[XH];
-  __shared__ __align__(16) uint16_t s_bits[WS_ROWS * 32];
+  // sign bits, 36 halfwords a row: the four lanes that store one ballot write
+  // rows 4 apart, which a 32-halfword stride would put in one bank
+  constexpr int BS = 36;
+  __shared__ __align__(16) uint16_t s_bits[WS_ROWS * BS];
   const int wv = threadIdx.x / 64, l = __lane_id(), ri = l % 16, g = l / 16;
   const int64_t nblk = (M + WS_ROWS - 1) / WS_ROWS;
   uint4 xr[PREF ? PER : 1];
@@ -332,63 +339,85 @@ __global__ __launch_bounds__(WS_T) void k_mlp_ws(const T* __restrict__ X, int64_
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const uint64_t m = __ballot(acc[rt][cb][r] + bc >= 0.f);
-            if (l < 4) s_bits[(16 * rt + 4 * l + r) * 32 + c0 / 16] = (uint16_t)(m >> (16 * l));
+            if (l < 4) s_bits[(16 * rt + 4 * l + r) * BS + c0 / 16] = (uint16_t)(m >> (16 * l));
           }
       }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < WS_ROWS * 8; e += WS_T) {
       const int r = e / 8, w = e % 8;
-      if (r0 + r < M) SK[(r0 + r) * 8 + w] = *(const uint64_t*)(s_bits + r * 32 + 4 * w);
+      if (r0 + r < M) SK[(r0 + r) * 8 + w] = *(const uint64_t*)(s_bits + r * BS + 4 * w);
     }
   }
 }
 
 // C = alpha * op(A) * op(B) + beta * C, FP32, row-major storage; op(A)[m][k] =
-// A[m*sam + k*sak], op(B)[k][n] = B[k*sbk + n*sbn].  64x64 tiles, 4x4 per thread.
+// A[m*sam + k*sak], op(B)[k][n] = B[k*sbk + n*sbn]; on v_mfma_f32_16x16x4_f32
+// (FP32 operands and sums).  64x64 tiles, four wavefronts of 32x32 (2 x 2 MFMA
+// tiles); K in LDS steps of 16.
+// Lane l of a 16x16x4 product holds A[l % 16][l / 16] and B[l / 16][l % 16]
+// and returns C[4 (l / 16) + r][l % 16] in register r.  Tile loads run along
+// whichever index of the operand has unit stride, so they are coalesced.
 __global__ __launch_bounds__(256) void k_sgemm(int M, int N, int K, float alpha, const float* __restrict__ A,
                                                int64_t sam, int64_t sak, const float* __restrict__ B,
                                                int64_t sbk, int64_t sbn, float beta, float* __restrict__ C,
                                                int64_t ldc) {
-  __shared__ float As[16][64 + 1];
-  __shared__ float Bs[16][64 + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  constexpr int LS = 64 + 16;  // row stride of the LDS tiles
+  __shared__ float As[16][LS];
+  __shared__ float Bs[16][LS];
+  const int l = __lane_id(), wv = threadIdx.x / 64, wm = wv / 2, wn = wv % 2;
+  const int i16 = l % 16, kq = l / 16;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  float acc[4][4] = {};
+  const bool a_k = sak == 1, b_k = sbk == 1;  // unit stride along k
+  float4v acc[2][2];
+#pragma unroll
+  for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < 2; ++tn) acc[tm][tn] = (float4v){0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int i = threadIdx.x; i < 16 * 64; i += 256) {
-      const int kk = i / 64, mm = i % 64;
-      const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.f;
-      const int n = n0 + mm;
-      Bs[kk][mm] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = threadIdx.x + 256 * u;
+      {
+        const int kk = a_k ? i % 16 : i / 64, mm = a_k ? i / 16 : i % 64;
+        const int m = m0 + mm, k = k0 + kk;
+        As[kk][mm] = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.f;
+      }
+      {
+        const int kk = b_k ? i % 16 : i / 64, nn = b_k ? i / 16 : i % 64;
+        const int n = n0 + nn, k = k0 + kk;
+        Bs[kk][nn] = (n < N && k < K) ? B[(int64_t)k * sbk + (int64_t)n * sbn] : 0.f;
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
+    for (int kk = 0; kk < 16; kk += 4) {
+      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = As[kk][ty * 4 + i];
-        b[i] = Bs[kk][tx * 4 + i];
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[kk + kq][32 * wm + 16 * t + i16];
+        b[t] = Bs[kk + kq][32 * wn + 16 * t + i16];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int tm = 0; tm < 2; ++tm)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int tn = 0; tn < 2; ++tn)
+          acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[tm], b[tn], acc[tm][tn], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int tm = 0; tm < 2; ++tm)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-      if (m < M && n < N) {
-        float* c = C + (int64_t)m * ldc + n;
-        *c = alpha * acc[i][j] + (beta != 0.f ? beta * *c : 0.f);
+    for (int tn = 0; tn < 2; ++tn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 32 * wm + 16 * tm + 4 * kq + r, n = n0 + 32 * wn + 16 * tn + i16;
+        if (m < M && n < N) {
+          float* c = C + (int64_t)m * ldc + n;
+          *c = alpha * acc[tm][tn][r] + (beta != 0.f ? beta * *c : 0.f);
+        }
       }
-    }
 }
 
 __global__ void k_tanh(const float* __restrict__ z, int64_t n, float slope, float* __restrict__ c) {

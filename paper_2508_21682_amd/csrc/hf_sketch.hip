@@ -84,7 +84,10 @@ __global__ __launch_bounds__(256) void srp_kernel(const T* __restrict__ X, int64
 // (512 x 64) are staged in LDS; the next step's global loads are issued
 // before the current step's products.  Sign bits are gathered with ballots.
 typedef int int4v __attribute__((ext_vector_type(4)));
-constexpr int SM_ROWS = 64, SM_K = 32, SM_PAD = 80;  // LDS row: 32 hi | 32 lo bytes + 16 pad (banks)
+// LDS row: 32 hi | 32 lo bytes + 32 pad, so rows sit 32 bytes past a multiple
+// of 256 and the 16-row x 4-chunk fragment reads hit distinct banks; sign-bit
+// rows of 36 halfwords (the four lanes storing one ballot write rows 4 apart)
+constexpr int SM_ROWS = 64, SM_K = 32, SM_PAD = 96, SM_BS = 36;
 
 template <class T>
 __device__ __forceinline__ void srp_load_x(const T* __restrict__ X, int64_t row, int d, int c, uint4 (&v)[2]) {
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
                                                        uint64_t* __restrict__ out) {
   __shared__ __align__(16) int8_t s_x[SM_ROWS * SM_PAD];
   __shared__ __align__(16) int8_t s_r[512 * SM_PAD];
-  __shared__ __align__(16) uint16_t s_bits[SM_ROWS * 32];
+  __shared__ __align__(16) uint16_t s_bits[SM_ROWS * SM_BS];
   const int wv = threadIdx.x / 64, l = __lane_id(), ri = l % 16, g = l / 16;
   const int64_t p0 = (int64_t)blockIdx.x * SM_ROWS;
   // staging roles: row xr, coordinates 8 xc .. 8 xc + 7 of the step; and
@@ -193,12 +196,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const uint64_t m = __ballot(acc[rt][cb][r] >= 0);
-        if (l < 4) s_bits[(16 * rt + 4 * l + r) * 32 + 8 * wv + cb] = (uint16_t)(m >> (16 * l));
+        if (l < 4) s_bits[(16 * rt + 4 * l + r) * SM_BS + 8 * wv + cb] = (uint16_t)(m >> (16 * l));
       }
   __syncthreads();
   for (int e = threadIdx.x; e < SM_ROWS * 8; e += 256) {
     const int r = e / 8, w = e % 8;
-    if (p0 + r < N) out[(p0 + r) * 8 + w] = *(const uint64_t*)(s_bits + r * 32 + 4 * w);
+    if (p0 + r < N) out[(p0 + r) * 8 + w] = *(const uint64_t*)(s_bits + r * SM_BS + 4 * w);
   }
 }
 
@@ -286,6 +289,17 @@ hf_status srp_sketch(const void* X, hf_dtype dt, int64_t N, int d, int e, uint64
     return HF_OK;
   };
   if (R_dev) return launch(R_dev);  // resident (a forest's): nothing to generate, upload or wait for
+  if (d % 16 == 0 && getenv("HF_SRP_VALU") == nullptr) {
+    // the int8 matrix-core kernel, its projection in the call's workspace
+    std::vector<int8_t> Rb = srp_matrix_i8(d, sketch_seed);
+    int8_t* dRb;
+    HF_TRY(ws.alloc(&dRb, Rb.size()));
+    HIP_TRY(hipMemcpyAsync(dRb, Rb.data(), Rb.size(), hipMemcpyHostToDevice, ws.stream));
+    HF_TRY(srp_sketch_mfma(X, dt, N, d, e, dRb, out, ws.stream));
+    // the host copy of Rb must outlive the async upload
+    HIP_TRY(hipStreamSynchronize(ws.stream));
+    return HF_OK;
+  }
   std::vector<uint64_t> Rt = srp_matrix(d, sketch_seed);
   uint64_t* dRt;
   HF_TRY(ws.alloc(&dRt, Rt.size()));

@@ -14,7 +14,7 @@ and on properties that hold at any size:
   |E| is the size of the +-h expansion of C2; the returned ids are the top-k
   of E by FP64 inner product (near-ties of the k-th score aside).
 
-The 1M x 384 plain graph (6 orders, window +-32) is small enough for the
+The 1M x 384 plain graph (16 orders, window +-32) is small enough for the
 oracle to sort in full: its sampled rows are compared exactly.  The 3M x 384
 graph in the benchmark's configuration (228 orders, +-160, k=15) is checked
 on sampled rows: cosines equal FP64 recomputations, sorted, distinct
@@ -149,15 +149,15 @@ def test_search_23M_sampled(hf, orc):
 
 
 def test_graph_1M_against_oracle(hf, orc):
-    """The 1M x 384 plain graph (6 orders, window +-32, k=15), 1,000 sampled rows exact."""
+    """The 1M x 384 plain graph (16 orders, window +-32, k=15), 1,000 sampled rows exact."""
     import torch
 
     w = datagen.WORKLOADS["graph-1Mx384"]
     print("drawing 1M x 384 on the host", flush=True)
     x = datagen.mixture(w["n"], w["d"], w["n_comp"], w["sigma"], w["seed"], dtype=np.float16)
-    gi, gs = hf.knn_graph(torch.from_numpy(x).cuda(), 6, 32, 15, 3)
+    gi, gs = hf.knn_graph(torch.from_numpy(x).cuda(), 16, 32, 15, 3)
     print("oracle orders", flush=True)
-    orders, _ = orc.graph_orders(x, 6, 3)
+    orders, _ = orc.graph_orders(x, 16, 3)
     rows = np.random.default_rng(1).choice(w["n"], 1000, replace=False)
     oi, os_, _ = orc.graph_rows(x, orders, 32, 15, rows)
     gi, gs = gi.cpu().numpy()[rows], gs.cpu().numpy()[rows]

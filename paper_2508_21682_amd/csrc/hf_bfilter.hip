@@ -635,48 +635,28 @@ hf_status bfilter_run(const hf_forest* f, int T, int len, int64_t nb, const uint
   HF_LAUNCH_CHECK();
   k_brow_scan<<<(unsigned)nbk, BS_T, 0, s>>>(cnt, nb, tot);
   HF_LAUNCH_CHECK();
-  const char* ce = getenv("HF_FILTER_CHUNK");
-  const uint32_t chunk = (uint32_t)std::max(256, std::min(1 << 16, ce ? atoi(ce) : 8192));
+  // records per chunk of the scoring kernel's work lists
+  constexpr uint32_t chunk = 8192;
   k_bplan<<<1, BS_T, 0, s>>>(tot, nbk, nbx, chunk, base, cumx, next);
   HF_LAUNCH_CHECK();
   // entries counting-sorted per pass of the scatter kernel, 16,384 at a
-  // time: 1024 threads x 16, or 512 x 32 (two workgroups a CU; measured no
+  // time by 1024 threads (512 x 32, two workgroups a CU, measured no
   // faster: 3.22 against 3.21 ms per 10,000 queries at 1,280 x 70)
-  const char* ste = getenv("HF_SCATTER_T");
-  const int sct = ste && atoi(ste) == 512 ? 512 : 1024;
   const size_t sc_ch = 16384;
   const size_t sc_lds = sizeof(uint32_t) * (3 * (size_t)nbk + T + sc_ch);
-  if (sct == 1024) {
-    if (sc_lds + 1024 > 64 * 1024)  // dynamic + static LDS above the default limit
-      HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<1024, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)sc_lds));
-    k_bscatter<1024, 16><<<(unsigned)nb, 1024, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
-  } else {
-    if (sc_lds + 1024 > 64 * 1024)
-      HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<512, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)sc_lds));
-    k_bscatter<512, 32><<<(unsigned)nb, 512, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
-  }
+  if (sc_lds + 1024 > 64 * 1024)  // dynamic + static LDS above the default limit
+    HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<1024, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sc_lds));
+  k_bscatter<1024, 16><<<(unsigned)nb, 1024, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
   HF_LAUNCH_CHECK();
   int dev = 0, ncu = 256;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const unsigned grid = (unsigned)std::max(BF_XCD, (ncu * 8 + BF_XCD - 1) / BF_XCD * BF_XCD);
-  // record blocks of 64 in flight per wavefront (tuning)
-  const char* sbe = getenv("HF_SCORE_SB");
-  const int sb = sbe ? atoi(sbe) : 2;
-  if (sb == 4)
-    k_bscore<4><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
-                                      capc);
-  else if (sb == 3)
-    k_bscore<3><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
-                                      capc);
-  else if (sb == 1)
-    k_bscore<1><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
-                                      capc);
-  else
-    k_bscore<2><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
-                                      capc);
+  // two record blocks of 64 in flight per wavefront (three or four: lower
+  // occupancy, slower)
+  k_bscore<2><<<grid, BF_T, 0, s>>>(rec, base, tot, cumx, nbx, bb, chunk, next, f->sk_pos, qsk, tau, cand, ccnt,
+                                    capc);
   HF_LAUNCH_CHECK();
   const size_t sel_lds = sizeof(uint64_t) * (size_t)capc;
   switch (capc / BF_SEL_T) {

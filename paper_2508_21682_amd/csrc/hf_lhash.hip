@@ -164,14 +164,6 @@ __global__ __launch_bounds__(256) void k_mlp(const T* __restrict__ A, int64_t M,
   }
 }
 
-// Encoder: both layers fused, 64 rows per workgroup.  The rows (as BF16),
-// then in the same LDS their hidden activations, stay on chip; each
-// wavefront computes a quarter of the columns of a layer for all 64 rows, so
-// a weight element is read once per workgroup (from L2, as the B operand of
-// v_mfma_f32_16x16x32_bf16).  The 512 output signs of each row are gathered
-// with ballots into an LDS bit array and stored as 8 words.  D: input
-// dimension (multiple of 32); HID: hidden units (multiple of 64).  The sums
-// run in the same order as the two-kernel path, so the sketches are equal.
 // 8 values of T as BF16, from the raw bytes of one (half) or two (float) uint4
 template <class T>
 __device__ __forceinline__ uint4 raw_to_bf16(uint4 r0, uint4 r1) {

@@ -813,7 +813,7 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU: multi-GPU runs are not part of this build (got --gpus %d)"
+        print("bench.py measures one GPU; the library has no multi-GPU path (got --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.k is None:

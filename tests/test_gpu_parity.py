@@ -139,16 +139,23 @@ def test_hilbert_sort_single_point(hf):
 
 # ------------------------------------------------------------------ sketches
 @pytest.mark.parametrize("dtype,d", [(np.float16, 384), (np.float32, 32), (np.float32, 70)])
-def test_srp_parity(hf, orc, dtype, d):
+def test_srp_parity(hf, orc, dtype, d, monkeypatch):
+    """d a multiple of 16 runs the int8 matrix-core kernel, d = 70 the vector-ALU
+    one; with HF_SRP_VALU set every d takes the vector-ALU kernel.  777 rows:
+    a ragged last block of 64."""
     x = datagen.mixture(777, d, 3, 0.1, 41, dtype=dtype)
     e = orc.quant_exp(x)
     want = orc.srp(x, e, 1234)
-    got = hf.srp_sketch(dev(x), e, 1234).cpu().numpy().view(np.uint64)
-    assert (got == want).all()
     # queries with larger values than the data clamp identically
     want2 = orc.srp(x * 3, e, 1234)
-    got2 = hf.srp_sketch(dev(x * 3), e, 1234).cpu().numpy().view(np.uint64)
-    assert (got2 == want2).all()
+    for valu in (False, True):
+        if valu:
+            monkeypatch.setenv("HF_SRP_VALU", "1")
+        got = hf.srp_sketch(dev(x), e, 1234).cpu().numpy().view(np.uint64)
+        assert (got == want).all(), valu
+        got2 = hf.srp_sketch(dev(x * 3), e, 1234).cpu().numpy().view(np.uint64)
+        assert (got2 == want2).all(), valu
+    monkeypatch.delenv("HF_SRP_VALU")
 
 
 # ------------------------------------------------------------------ forest + search

@@ -639,19 +639,29 @@ hf_status bfilter_run(const hf_forest* f, int T, int len, int64_t nb, const uint
   constexpr uint32_t chunk = 8192;
   k_bplan<<<1, BS_T, 0, s>>>(tot, nbk, nbx, chunk, base, cumx, next);
   HF_LAUNCH_CHECK();
-  // entries counting-sorted per pass of the scatter kernel, 16,384 at a
-  // time by 1024 threads (512 x 32, two workgroups a CU, measured no
-  // faster: 3.22 against 3.21 ms per 10,000 queries at 1,280 x 70)
-  const size_t sc_ch = 16384;
-  const size_t sc_lds = sizeof(uint32_t) * (3 * (size_t)nbk + T + sc_ch);
-  if (sc_lds + 1024 > 64 * 1024)  // dynamic + static LDS above the default limit
-    HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<1024, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)sc_lds));
-  k_bscatter<1024, 16><<<(unsigned)nb, 1024, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
-  HF_LAUNCH_CHECK();
-  int dev = 0, ncu = 256;
+  int dev = 0, ncu = 256, max_lds = 64 * 1024;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // entries counting-sorted per pass of the scatter kernel by 1024 threads:
+  // 32,768 at a time when LDS holds them, else 16,384.  Longer passes give
+  // each (bucket, query) run fewer, longer pieces: the stage took 10.7
+  // against 11.2 ms per 10,000 queries at 1,280 x 70 (512 x 32, two
+  // workgroups a CU: no faster than 1024 x 16)
+  const size_t sc_fixed = 3 * (size_t)nbk + T;
+  const bool sc_big = sizeof(uint32_t) * (sc_fixed + 32768) + 1024 <= (size_t)max_lds;
+  const size_t sc_lds = sizeof(uint32_t) * (sc_fixed + (sc_big ? 32768 : 16384));
+  if (sc_big) {
+    HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<1024, 32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sc_lds));
+    k_bscatter<1024, 32><<<(unsigned)nb, 1024, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
+  } else {
+    if (sc_lds + 1024 > 64 * 1024)  // dynamic + static LDS above the default limit
+      HIP_TRY(hipFuncSetAttribute((const void*)k_bscatter<1024, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)sc_lds));
+    k_bscatter<1024, 16><<<(unsigned)nb, 1024, sc_lds, s>>>(em, T, win, bb, nbk, nb, cnt, base, rec);
+  }
+  HF_LAUNCH_CHECK();
   const unsigned grid = (unsigned)std::max(BF_XCD, (ncu * 8 + BF_XCD - 1) / BF_XCD * BF_XCD);
   // two record blocks of 64 in flight per wavefront (three or four: lower
   // occupancy, slower)

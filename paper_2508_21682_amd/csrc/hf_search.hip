@@ -753,7 +753,8 @@ __global__ __launch_bounds__(RR_T) void k_rerank(const T* __restrict__ Xp, int64
 #pragma unroll
           for (int m = 0; m < MCH; ++m) {
             const int c = gl + 16 * m;
-            raw[u][m] = (e < E && c < nch) ? *(const uint4*)(row + c * EPC) : make_uint4(0, 0, 0, 0);
+            // unconditional (past E the row is row 0, its score never stored)
+            raw[u][m] = *(const uint4*)(row + (c < nch ? c : 0) * EPC);
           }
         }
 #pragma unroll
